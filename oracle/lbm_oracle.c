@@ -1,0 +1,328 @@
+/*
+ * FP64 reference implementation of the high-order lattice Boltzmann BGK
+ * update with the kinetic diffuse-reflection wall of Meng & Zhang
+ * (arXiv:1209.5201).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle: a plain, slow,
+ * literal rendering of the paper's equations, used to check the product
+ * path.  Only the tests, the smoke check and the benchmark's CPU-baseline
+ * leg may load it.  It shares no code, header or table with the product.
+ *
+ * Geometry (the paper's Couette set-up, Sec. IV, with the wall placed half a
+ * grid spacing outside the first fluid row, Sec. III):
+ *   - nx periodic columns x, ny fluid rows y = 0..ny-1;
+ *   - bottom wall below row 0, normal +y; ghost layer l (l = 0..N-1) is the
+ *     row -(l+1);
+ *   - top wall above row ny-1, normal -y; ghost layer l is the row ny+l;
+ *   - z is a single periodic plane, so z-streaming is the identity while c_z
+ *     still enters the equilibrium and the moments (3-D velocity sets).
+ *
+ * State: f~ of Sec. II (the variable that removes the implicitness of the
+ * trapezoidal scheme), stored per node as Q consecutive doubles,
+ * f[(y*nx + x)*Q + a].
+ *
+ * One step (Eq. (eq:scheme) with Sec. III):
+ *   1. moments of f~ (Eq. (eq:summac)), f^eq from Eq. (eq:feq);
+ *   2. post-collision f* = f~ - (f~ - f^eq)/(tau + 1/2)   (dt = 1);
+ *   3. stream every f* along its integer velocity; what leaves the fluid
+ *      lands in an explicit ghost array as the incoming f^I (Sec. III);
+ *   4. per ghost column, pool all incoming mass over all layers and re-emit
+ *      it along every outgoing velocity of every layer in proportion to the
+ *      wall Maxwellian, Eq. (eq:dkboundary);
+ *   5. the outgoing f^O stream into the fluid in the same step.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int Q, D, eq_order, thermal;
+    const int *e;      /* Q rows of (ex, ey, ez) */
+    const double *w;   /* Q weights */
+    double r;          /* c_a = r * e_a */
+} olat;
+
+/* Eq. (eq:feq): g^eq_a(u, T), truncated after the requested order.
+ * The terms are grouped exactly as printed in the paper. */
+static double geq(const olat *L, int a, const double u[3], double T)
+{
+    double c[3], cu = 0.0, uu = 0.0, cc = 0.0;
+    double D = (double)L->D;
+    double th = T - 1.0;
+    double g;
+    int i;
+    for (i = 0; i < 3; ++i) {
+        c[i] = L->r * (double)L->e[3 * a + i];
+        cu += c[i] * u[i];
+        uu += u[i] * u[i];
+        cc += c[i] * c[i];
+    }
+    g = 1.0 + cu;
+    if (L->eq_order >= 2)
+        g += 0.5 * (cu * cu - uu + th * (cc - D));
+    if (L->eq_order >= 3)
+        g += cu / 6.0 * (cu * cu - 3.0 * uu + 3.0 * th * (cc - D - 2.0));
+    if (L->eq_order >= 4) {
+        g += (cu * cu * cu * cu - 6.0 * cu * cu * uu + 3.0 * uu * uu) / 24.0;
+        g += th / 4.0 * ((cc - D - 2.0) * (cu * cu - uu) - 2.0 * cu * cu);
+        g += th * th / 8.0 * (cc * cc - 2.0 * (D + 2.0) * cc + D * (D + 2.0));
+    }
+    return L->w[a] * g;
+}
+
+/* Eq. (eq:summac): density, velocity and temperature of one node.
+ * Isothermal lattices use T = 1 (Sec. II, after Eq. (eq:feq)). */
+static void node_moments(const olat *L, const double *f, double *rho,
+                         double u[3], double *T)
+{
+    double m0 = 0.0, m1[3] = {0.0, 0.0, 0.0};
+    int a, i;
+    for (a = 0; a < L->Q; ++a) {
+        m0 += f[a];
+        for (i = 0; i < 3; ++i)
+            m1[i] += f[a] * L->r * (double)L->e[3 * a + i];
+    }
+    *rho = m0;
+    for (i = 0; i < 3; ++i)
+        u[i] = m1[i] / m0;
+    if (L->thermal) {
+        double e2 = 0.0;
+        for (a = 0; a < L->Q; ++a) {
+            double C2 = 0.0;
+            for (i = 0; i < 3; ++i) {
+                double Ci = L->r * (double)L->e[3 * a + i] - u[i];
+                C2 += Ci * Ci;
+            }
+            e2 += f[a] * C2;
+        }
+        *T = e2 / (m0 * (double)L->D);
+    } else {
+        *T = 1.0;
+    }
+}
+
+static int max_ey(const olat *L)
+{
+    int a, n = 0;
+    for (a = 0; a < L->Q; ++a)
+        if (abs(L->e[3 * a + 1]) > n)
+            n = abs(L->e[3 * a + 1]);
+    return n;
+}
+
+static int wrap(int x, int nx)
+{
+    int m = x % nx;
+    return m < 0 ? m + nx : m;
+}
+
+/* One full step.  flux (may be NULL) receives, summed over all ghost
+ * columns: incoming and outgoing mass of the bottom wall, then of the top. */
+static void one_step(const olat *L, int nx, int ny, double omega,
+                     const double *gb, const double *gt,
+                     double *f, double *fs, double *fn,
+                     double *ghb, double *ght, double *flux)
+{
+    const int Q = L->Q, N = max_ey(L);
+    const size_t nodes = (size_t)nx * (size_t)ny;
+    double Db = 0.0, Dt = 0.0;
+    double in_b = 0.0, out_b = 0.0, in_t = 0.0, out_t = 0.0;
+    size_t n;
+    int x, y, a, l;
+
+    /* 1-2. collision at every fluid node */
+    for (n = 0; n < nodes; ++n) {
+        double rho, u[3], T;
+        node_moments(L, f + n * Q, &rho, u, &T);
+        for (a = 0; a < Q; ++a) {
+            double feq = rho * geq(L, a, u, T);
+            fs[n * Q + a] = f[n * Q + a] - omega * (f[n * Q + a] - feq);
+        }
+    }
+
+    /* 3. streaming: fluid -> fluid, or fluid -> ghost (incoming f^I) */
+    memset(fn, 0, nodes * Q * sizeof(double));
+    memset(ghb, 0, (size_t)N * nx * Q * sizeof(double));
+    memset(ght, 0, (size_t)N * nx * Q * sizeof(double));
+    for (y = 0; y < ny; ++y)
+        for (x = 0; x < nx; ++x)
+            for (a = 0; a < Q; ++a) {
+                int xd = wrap(x + L->e[3 * a], nx);
+                int yd = y + L->e[3 * a + 1];
+                double v = fs[((size_t)y * nx + x) * Q + a];
+                if (yd >= 0 && yd < ny)
+                    fn[((size_t)yd * nx + xd) * Q + a] = v;
+                else if (yd < 0)
+                    ghb[((size_t)(-yd - 1) * nx + xd) * Q + a] = v;
+                else
+                    ght[((size_t)(yd - ny) * nx + xd) * Q + a] = v;
+            }
+
+    /* 4. denominators of Eq. (eq:dkboundary): sum over layers l and over the
+     * velocities that leave the wall at layer l, (c - u_w).n > l. */
+    for (l = 0; l < N; ++l)
+        for (a = 0; a < Q; ++a) {
+            if (L->e[3 * a + 1] > l)      /* bottom: n = +y */
+                Db += gb[a];
+            if (-L->e[3 * a + 1] > l)     /* top: n = -y */
+                Dt += gt[a];
+        }
+
+    /* 4-5. per ghost column: pool the incoming mass, emit f^O, stream it */
+    for (x = 0; x < nx; ++x) {
+        double Mb = 0.0, Mt = 0.0;
+        for (l = 0; l < N; ++l)
+            for (a = 0; a < Q; ++a) {
+                if (L->e[3 * a + 1] < -l)     /* (c'-u_w).n < -l, n = +y */
+                    Mb += ghb[((size_t)l * nx + x) * Q + a];
+                if (-L->e[3 * a + 1] < -l)    /* n = -y */
+                    Mt += ght[((size_t)l * nx + x) * Q + a];
+            }
+        in_b += Mb;
+        in_t += Mt;
+        for (l = 0; l < N; ++l)
+            for (a = 0; a < Q; ++a) {
+                if (L->e[3 * a + 1] > l) {
+                    double fo = Mb / Db * gb[a];
+                    int xd = wrap(x + L->e[3 * a], nx);
+                    int yd = -(l + 1) + L->e[3 * a + 1];
+                    fn[((size_t)yd * nx + xd) * Q + a] = fo;
+                    out_b += fo;
+                }
+                if (-L->e[3 * a + 1] > l) {
+                    double fo = Mt / Dt * gt[a];
+                    int xd = wrap(x + L->e[3 * a], nx);
+                    int yd = ny + l + L->e[3 * a + 1];
+                    fn[((size_t)yd * nx + xd) * Q + a] = fo;
+                    out_t += fo;
+                }
+            }
+    }
+    memcpy(f, fn, nodes * Q * sizeof(double));
+    if (flux) {
+        flux[0] = in_b;
+        flux[1] = out_b;
+        flux[2] = in_t;
+        flux[3] = out_t;
+    }
+}
+
+/* ---------------------------------------------------------------- API --- */
+
+/* g^eq_a(u, T) for all a (rho = 1), Eq. (eq:feq). */
+void orc_geq(int Q, int D, int eq_order, int thermal, const int *e,
+             const double *w, double r, const double *u, double T,
+             double *out)
+{
+    olat L = {Q, D, eq_order, thermal, e, w, r};
+    int a;
+    for (a = 0; a < Q; ++a)
+        out[a] = geq(&L, a, u, thermal ? T : 1.0);
+}
+
+/* f~(0) = f^eq(rho0, u0, T0) at every node (fields of nx*ny values,
+ * row-major with x fastest; u0 holds three such fields x, y, z). */
+void orc_init(int Q, int D, int eq_order, int thermal, const int *e,
+              const double *w, double r, int nx, int ny, const double *rho0,
+              const double *u0, const double *T0, double *f)
+{
+    olat L = {Q, D, eq_order, thermal, e, w, r};
+    size_t nodes = (size_t)nx * (size_t)ny, n;
+    int a;
+    for (n = 0; n < nodes; ++n) {
+        double u[3] = {u0[n], u0[nodes + n], u0[2 * nodes + n]};
+        double T = thermal ? T0[n] : 1.0;
+        for (a = 0; a < Q; ++a)
+            f[n * Q + a] = rho0[n] * geq(&L, a, u, T);
+    }
+}
+
+/* Advance f~ by nsteps.  wall_b/wall_t = {ux, uz, T} of each wall
+ * (tangential velocities only).  tau is the relaxation time in time steps;
+ * +inf gives the collisionless limit.  flux (may be NULL): 4 doubles per
+ * step, see one_step().  Returns 0, or -1 on allocation failure. */
+int orc_run(int Q, int D, int eq_order, int thermal, const int *e,
+            const double *w, double r, int nx, int ny, double tau,
+            const double *wall_b, const double *wall_t, double *f,
+            long nsteps, double *flux)
+{
+    olat L = {Q, D, eq_order, thermal, e, w, r};
+    const int N = max_ey(&L);
+    const size_t nodes = (size_t)nx * (size_t)ny;
+    double omega = 1.0 / (tau + 0.5);
+    double ub[3] = {wall_b[0], 0.0, wall_b[1]};
+    double ut[3] = {wall_t[0], 0.0, wall_t[1]};
+    double *gb = malloc(Q * sizeof(double));
+    double *gt = malloc(Q * sizeof(double));
+    double *fs = malloc(nodes * Q * sizeof(double));
+    double *fn = malloc(nodes * Q * sizeof(double));
+    double *ghb = malloc((size_t)N * nx * Q * sizeof(double));
+    double *ght = malloc((size_t)N * nx * Q * sizeof(double));
+    long s;
+    int a, rc = 0;
+    if (!gb || !gt || !fs || !fn || !ghb || !ght) {
+        rc = -1;
+        goto done;
+    }
+    /* wall Maxwellians at (u_w, T_w) with unit density (Sec. III, R_D) */
+    for (a = 0; a < Q; ++a) {
+        gb[a] = geq(&L, a, ub, thermal ? wall_b[2] : 1.0);
+        gt[a] = geq(&L, a, ut, thermal ? wall_t[2] : 1.0);
+    }
+    for (s = 0; s < nsteps; ++s)
+        one_step(&L, nx, ny, omega, gb, gt, f, fs, fn, ghb, ght,
+                 flux ? flux + 4 * s : NULL);
+done:
+    free(gb);
+    free(gt);
+    free(fs);
+    free(fn);
+    free(ghb);
+    free(ght);
+    return rc;
+}
+
+/* Output fields of f~ at one time level (Eq. (eq:summac)).  The stress and
+ * heat flux of the original f follow from f - f^eq = (f~ - f^eq) tau/(tau+1/2)
+ * (the change of variable of Sec. II); the moments are linear in f, so
+ *   X[f] = X[f^eq] + tau/(tau + 1/2) (X[f~] - X[f^eq]).
+ * out: 9 fields of nx*ny: rho, ux, uy, uz, T, sigma_xy, q_x, q_y, q_z. */
+void orc_moments(int Q, int D, int eq_order, int thermal, const int *e,
+                 const double *w, double r, int nx, int ny, double tau,
+                 const double *f, double *out)
+{
+    olat L = {Q, D, eq_order, thermal, e, w, r};
+    const size_t nodes = (size_t)nx * (size_t)ny;
+    double k = isinf(tau) ? 1.0 : tau / (tau + 0.5);
+    size_t n;
+    int a, i;
+    for (n = 0; n < nodes; ++n) {
+        const double *fn = f + n * Q;
+        double rho, u[3], T;
+        double sig_t = 0.0, sig_e = 0.0, q_t[3] = {0, 0, 0}, q_e[3] = {0, 0, 0};
+        node_moments(&L, fn, &rho, u, &T);
+        for (a = 0; a < Q; ++a) {
+            double C[3], C2 = 0.0, feq = rho * geq(&L, a, u, T);
+            for (i = 0; i < 3; ++i) {
+                C[i] = L.r * (double)L.e[3 * a + i] - u[i];
+                C2 += C[i] * C[i];
+            }
+            /* the xy entry of the trace-free tensor C<i C j> is C_x C_y */
+            sig_t += fn[a] * C[0] * C[1];
+            sig_e += feq * C[0] * C[1];
+            for (i = 0; i < 3; ++i) {
+                q_t[i] += 0.5 * fn[a] * C2 * C[i];
+                q_e[i] += 0.5 * feq * C2 * C[i];
+            }
+        }
+        out[0 * nodes + n] = rho;
+        out[1 * nodes + n] = u[0];
+        out[2 * nodes + n] = u[1];
+        out[3 * nodes + n] = u[2];
+        out[4 * nodes + n] = T;
+        out[5 * nodes + n] = sig_e + k * (sig_t - sig_e);
+        out[6 * nodes + n] = q_e[0] + k * (q_t[0] - q_e[0]);
+        out[7 * nodes + n] = q_e[1] + k * (q_t[1] - q_e[1]);
+        out[8 * nodes + n] = q_e[2] + k * (q_t[2] - q_e[2]);
+    }
+}
