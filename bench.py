@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the fused stream-collide update on one MI355X.
+
+Workload: the 2-D bulk bandwidth case - D2Q17, 2048 x 2048 nodes, periodic
+in x, diffuse walls (at rest, T = 1) top and bottom, Kn = 0.05,
+rho = 1 + 1e-3 N(0,1) (seed 0), u = 0, FP32 populations.  One benchmark step
+is one time step of the whole grid (wall sums + fused update; the output
+fields, mass and residual are refreshed after the last step of the timed
+call).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: MLUPS (million lattice-node updates per second), the
+HBM roofline of the fused update kernel (algorithmic bytes 2*Q*4 per node,
+kernel time from HIP events over the timed region), and the FP64 oracle
+timed on the host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, published
+
+
+def traffic_from_profile(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor), if
+    one exists for this kernel build; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+        ent = data[kernel]
+        if ent.get("workload") != workload:
+            return None
+        src = os.path.join(ROOT, "paper_1209_5201_amd", "csrc", "lbm_kernels.hip")
+        import hashlib
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if ent.get("source_sha") != digest:
+            return None
+        return float(ent["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg, nsteps: int):
+    """The FP64 oracle on the host: same grid and start field, nsteps steps."""
+    import numpy as np  # noqa: F401
+    from oracle import oracle as O
+    from paper_1209_5201_amd import workloads as W
+    rho = W.c3_density(cfg["nx"], cfg["ny"], seed=cfg["seed"], amp=cfg["amp"])
+    case = O.OracleCase(cfg["lattice"], cfg["nx"], cfg["ny"],
+                        O.tau_from_kn(cfg["lattice"], cfg["ny"], cfg["kn"]),
+                        cfg["bottom"], cfg["top"], rho0=rho)
+    t0 = time.perf_counter()
+    case.run(nsteps)
+    dt = time.perf_counter() - t0
+    return {"value": cfg["nx"] * cfg["ny"] * nsteps / dt / 1e6, "unit": "MLUPS",
+            "cores": 1, "kind": "oracle",
+            "sample": "%s %dx%d FP64, %d steps (%.1f s), single-threaded C"
+                      % (cfg["lattice"], cfg["nx"], cfg["ny"], nsteps, dt)}
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
+    """Device-to-device copy rate (read + write bytes / time) as a practical
+    HBM ceiling, measured in the same run."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    e.synchronize()
+    return 2.0 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the single-GPU share is the "
+              "workload (a multi-GPU run would split x into slabs with a "
+              "3-column halo exchange, which this build does not implement)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import torch
+    import paper_1209_5201_amd as lbm
+    from paper_1209_5201_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    cfg = W.C3
+    nx, ny, lat = cfg["nx"], cfg["ny"], cfg["lattice"]
+    Q = lbm.lbm_lattice_info(lat)["Q"]
+    tau = lbm.lbm_tau_from_kn(lat, ny, cfg["kn"])
+    ch = lbm.Channel(lat, nx, ny, tau, cfg["bottom"], cfg["top"], prec=cfg["prec"])
+    ch.init(rho=W.c3_density(nx, ny, seed=cfg["seed"], amp=cfg["amp"]))
+    if args.warmup:
+        ch.step(args.warmup)
+    torch.cuda.synchronize()
+
+    lbm.lbm_set_timing(ch.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = lbm.lbm_kernel_time(ch.ctx)
+    lbm.lbm_set_timing(ch.ctx, False)
+    mass = ch.mass()
+
+    elapsed = t1 - t0
+    nodes = nx * ny
+    mlups = nodes * args.steps / elapsed / 1e6
+    upd_s = kt["update_ms"] / max(kt["update_launches"], 1) * 1e-3
+    alg_bytes = 2.0 * Q * 4 * nodes          # read Q + write Q FP32 populations
+    achieved = alg_bytes / upd_s / 1e9
+    kernel = "step_kernel<D2Q17, CF32, false>"
+    workload = "D2Q17 2048x2048 FP32"
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic_from_profile(kernel, workload),
+            "kernel": kernel, "kernel_us": round(upd_s * 1e6, 2),
+            "wall_kernel_us": round(kt["wall_ms"] / max(kt["wall_launches"], 1) * 1e3, 2),
+            "bytes_per_launch": alg_bytes}
+    line = {
+        "metric": "MLUPS (FP32 fused stream-collide, HBM roofline)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D bulk bandwidth: D2Q17 2048x2048, diffuse walls at rest, "
+                               "Kn=0.05, rho=1+1e-3 N(0,1) seed 0, FP32 populations",
+                   "nx": nx, "ny": ny, "lattice": lat, "precision": "fp32",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "copy_ref_GBps": round(copy_bandwidth(torch), 1),
+        "mass_after": mass,
+    }
+    ch.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,70 @@
+// Internal types shared by the host library and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbm {
+
+constexpr int kQMax = 121;
+constexpr int kFields = 9;          // rho, ux, uy, uz, T, sxy, qx, qy, qz
+constexpr int kBlock = 256;         // threads per block of the node kernels
+constexpr int kReduceBlocks = 512;  // partial sums of the FP64 reductions
+
+enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2, kFP16 = 3 };
+
+// Per-context constants, resident in device memory and read by the kernels
+// through a const __restrict__ pointer (wave-uniform, so scalar loads).
+// Populations are held as deviations g_q = f_q - w_q from the rest state
+// (rho = 1, u = 0, T = 1) in storage and in all arithmetic.
+struct Tables {
+  double gb[kQMax];   // g^eq(u_b, T_b), unit density: bottom-wall Maxwellian
+  double gt[kQMax];   // top-wall Maxwellian
+  double Db, Dt;      // sum over layers l and outgoing velocities of g^eq
+  double Wb, Wt;      // rest-state part of the pooled mass: sum of w over the
+                      // (velocity, row) pairs that cross each wall
+  float dec;          // 16-bit codecs: g = h * dec
+  float enc;          //                h = g * enc
+  float pad[2];
+};
+
+struct StepArgs {
+  const void* fin;      // deviations g* of the previous step (SoA planes)
+  void* fout;           // populations written by this step
+  const Tables* tab;
+  double* ratio;        // [2][nx]: pooled incoming mass / D per ghost column
+  double* mom;          // kFields x nodes output fields, or null
+  int nx, ny;
+  long long plane;      // elements between population planes
+  double omega;         // 1 / (tau + 1/2)
+  double kfac;          // tau / (tau + 1/2): f~ -> f conversion of sigma, q
+};
+
+struct ReduceArgs {
+  const double* mom;    // output fields of the current time
+  double* snap;         // ux, uy, uz, T at the previous residual point
+  double* partial;      // kReduceBlocks x 4
+  double* result;       // mass, sum du^2, sum dT^2, nonfinite count
+  long long nodes;
+};
+
+// Launchers (lbm_kernels.hip).  lattice: 0 D2Q16, 1 D2Q17, 2 D3Q121.
+hipError_t launch_wall(int lattice, int prec, const StepArgs& a, hipStream_t s);
+hipError_t launch_step(int lattice, int prec, const StepArgs& a, bool moments,
+                       hipStream_t s);
+// f~ = f^eq(fields) -> collide -> fout; also writes the output fields.
+// fields: rho, ux, uy, uz, T (5 x nodes doubles, may alias a.mom).
+hipError_t launch_init(int lattice, int prec, const StepArgs& a,
+                       const double* fields, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s);
+
+// Host helpers (no device work).
+// g^eq_q(u, T) of every velocity with unit density (wall Maxwellians).
+void host_geq(int lattice, const double u[3], double T, double* out);
+// Q, D, N (ghost layers), truncation order, r, e (Q x 3) and w (Q) of a set;
+// e and w may be null.  Returns -1 for an unknown lattice.
+int host_lattice(int lattice, int* Q, int* D, int* N, int* EQ, double* r, int* e, double* w);
+
+}  // namespace lbm

@@ -1,0 +1,261 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Metric (per output field): a field passes if
+    max |gpu - oracle| <= rtol * scale + atol,
+where scale is the largest magnitude of the physical quantity the field
+belongs to (velocity components share the largest |u_i|, heat-flux
+components the largest |q_i|; rho, T, sigma_xy their own): point-wise
+relative error is meaningless where a field crosses zero, and a component
+that is zero up to convergence or rounding (u_y of a steady Couette flow) is
+measured against the flow speed, not against its own noise.  The small
+absolute floor covers fields that are zero up to rounding everywhere (q of
+an isothermal set at t = 0): rounding of O(1) sums leaves ~1e-16 in FP64.
+Bars: FP64 rtol 1e-12 / atol 1e-15; FP32 rtol 1e-5 / atol 1e-9; 16-bit
+deviation storage per the tests below.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1209_5201_amd as lbm
+from paper_1209_5201_amd import workloads as W
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("rho", "ux", "uy", "uz", "T", "sxy", "qx", "qy", "qz")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+ATOL = {"fp64": 1e-15, "fp32": 1e-9}
+
+
+GROUPS = {"ux": ("ux", "uy", "uz"), "uy": ("ux", "uy", "uz"), "uz": ("ux", "uy", "uz"),
+          "qx": ("qx", "qy", "qz"), "qy": ("qx", "qy", "qz"), "qz": ("qx", "qy", "qz")}
+
+
+def field_err(got, want, k, atol=0.0):
+    """max |diff| / scale after removing the absolute floor."""
+    scale = max(np.abs(want[j]).max() for j in GROUPS.get(k, (k,)) if j in want)
+    diff = max(np.abs(got[k] - want[k]).max() - atol, 0.0)
+    return diff / scale if scale > 0 else diff
+
+
+def assert_fields(got, want, tol, fields=FIELDS, ctx="", atol=1e-15):
+    errs = {k: field_err(got, want, k, atol) for k in fields}
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, (ctx, bad, errs)
+    return errs
+
+
+def gpu_case(lat, nx, ny, tau, bottom, top, prec="fp64", fields=None):
+    ch = lbm.Channel(lat, nx, ny, tau, bottom, top, prec=prec)
+    if fields is not None:
+        rho, ux, uy, T = fields
+        ch.init(rho=rho, ux=ux, uy=uy, T=T)
+    return ch
+
+
+def oracle_case(lat, nx, ny, tau, bottom, top, fields=None):
+    if fields is None:
+        return O.OracleCase(lat, nx, ny, tau, bottom, top)
+    rho, ux, uy, T = fields
+    u0 = np.stack([ux, uy, np.zeros_like(ux)])
+    return O.OracleCase(lat, nx, ny, tau, bottom, top, rho0=rho, u0=u0, T0=T)
+
+
+LATS = ["D2Q16", "D2Q17", "D3Q121"]
+WALLS = {"D2Q16": ((-0.1, 0.0, 1.0), (0.1, 0.0, 1.0)),
+         "D2Q17": ((-0.1, 0.0, 1.0), (0.1, 0.0, 1.0)),
+         "D3Q121": ((-0.1, 0.03, 1.0), (0.1, 0.0, 1.1))}
+
+
+@pytest.mark.parametrize("lat", LATS)
+def test_fp64_random_start_several_tiles_ragged(lat):
+    # 37 x 24 = 888 nodes: 4 blocks of 256 threads with a ragged tail; x wraps
+    nx, ny = (37, 24) if lat != "D3Q121" else (13, 24)
+    say("case fp64 random", lat, nx, ny)
+    tau = 0.8
+    fields = W.random_fields(nx, ny, seed=3, thermal=(lat == "D3Q121"))
+    g = gpu_case(lat, nx, ny, tau, *WALLS[lat], fields=fields)
+    o = oracle_case(lat, nx, ny, tau, *WALLS[lat], fields=fields)
+    assert_fields(g.moments(), o.moments(), 1e-12, ctx="t=0")
+    for t in (1, 9, 30):
+        g.step(t)
+        o.run(t)
+        assert_fields(g.moments(), o.moments(), 1e-12, ctx="t=%d" % o.t)
+    assert abs(g.mass() - o.mass()) < 1e-12 * o.mass()
+    g.close()
+
+
+@pytest.mark.parametrize("lat", ["D2Q16", "D2Q17"])
+def test_c1_isothermal_couette_fp64(lat):
+    c = W.C1
+    say("case C1", lat)
+    tau_g = lbm.lbm_tau_from_kn(lat, c["ny"], c["kn"])
+    tau_o = O.tau_from_kn(lat, c["ny"], c["kn"])
+    assert abs(tau_g - tau_o) < 1e-14 * tau_o
+    g = gpu_case(lat, c["nx"], c["ny"], tau_g, c["bottom"], c["top"])
+    o = oracle_case(lat, c["nx"], c["ny"], tau_o, c["bottom"], c["top"])
+    g.step(c["steps"])
+    o.run(c["steps"])
+    assert_fields(g.moments(), o.moments(), 1e-12)
+    g.close()
+
+
+def run_windows_gpu(ch, tol, window, max_steps):
+    while ch.steps_done() < max_steps:
+        ch.step(window)
+        if ch.residual() < tol:
+            return ch.steps_done()
+    raise AssertionError("no convergence")
+
+
+def run_windows_oracle(oc, tol, window, max_steps, uref):
+    prev = oc.moments()
+    while oc.t < max_steps:
+        oc.run(window)
+        cur = oc.moments()
+        r = O.residual_rate(prev, cur, window, uref)
+        prev = cur
+        if r < tol:
+            return oc.t, cur
+    raise AssertionError("no convergence")
+
+
+@pytest.mark.parametrize("kn", [0.5, 0.1])
+def test_c2_thermal_couette_fp64_and_fp32(kn):
+    """D3Q121, 4 x 256, walls -0.2 (T=1) / +0.2 (T=1.1), run to a 1e-8
+    residual rate.  The problem is x-invariant, so the oracle runs one column
+    and every GPU column is compared with it."""
+    c = W.C2
+    lat = c["lattice"]
+    say("case C2", kn)
+    tau = O.tau_from_kn(lat, c["ny"], kn)
+    o = oracle_case(lat, 1, c["ny"], tau, c["bottom"], c["top"])
+    n_o, want = run_windows_oracle(o, c["tol"], c["window"], 200000, 0.2)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        g = gpu_case(lat, c["nx"], c["ny"], lbm.lbm_tau_from_kn(lat, c["ny"], kn),
+                     c["bottom"], c["top"], prec=prec)
+        n_g = run_windows_gpu(g, c["tol"], c["window"], 200000)
+        got = g.moments()
+        for k in FIELDS:
+            assert np.abs(got[k] - got[k][:, :1]).max() == 0.0, (prec, k)
+        col = {k: got[k][:, :1] for k in FIELDS}
+        if prec == "fp64":
+            assert n_g == n_o
+            assert_fields(col, want, tol, ctx=prec)
+        else:
+            assert abs(n_g - n_o) <= 2 * c["window"]
+            assert_fields(col, want, tol, ctx=prec, atol=ATOL[prec])
+        g.close()
+
+
+def test_mass_conservation_and_rest_state():
+    for lat in LATS:
+        say("case mass", lat)
+        tau = 0.7
+        fields = W.random_fields(9, 16, seed=4, thermal=(lat == "D3Q121"))
+        g = gpu_case(lat, 9, 16, tau, *WALLS[lat], fields=fields)
+        m0 = g.mass()
+        for _ in range(20):
+            g.step(1)
+            m = g.mass()
+            assert abs(m - m0) < 1e-13 * m0, (lat, m, m0)
+            m0 = m
+        g.close()
+        r = gpu_case(lat, 5, 12, 0.6, (0.0, 0.0, 1.0), (0.0, 0.0, 1.0))
+        r.step(50)
+        m = r.moments()
+        assert np.abs(m["rho"] - 1).max() < 1e-14
+        assert np.abs(m["ux"]).max() < 1e-14 and np.abs(m["uy"]).max() < 1e-14
+        r.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_c3_full_size_launch_against_tiled_oracle(prec, tol):
+    """The 2048 x 2048 bulk case in the benchmark's launch configuration.
+    The start density is drawn for 8 columns and tiled along x, so the exact
+    result is x-periodic with period 8 and the oracle runs one 8 x 2048
+    period; every GPU period is compared with it."""
+    c = W.C3
+    say("case C3 full size", prec)
+    nx, ny, P, steps = c["nx"], c["ny"], 8, 20
+    rho = W.c3_density(nx, ny, seed=c["seed"], amp=c["amp"], period_x=P)
+    g = lbm.Channel(c["lattice"], nx, ny, lbm.lbm_tau_from_kn(c["lattice"], ny, c["kn"]),
+                    c["bottom"], c["top"], prec=prec)
+    g.init(rho=rho)
+    g.step(steps)
+    got = g.moments()
+    o = O.OracleCase(c["lattice"], P, ny, O.tau_from_kn(c["lattice"], ny, c["kn"]),
+                     c["bottom"], c["top"], rho0=rho[:, :P])
+    o.run(steps)
+    want = o.moments()
+    # the signal is the deviation from the rest state: compare rho - 1
+    want["drho"] = want["rho"] - 1
+    got["drho"] = got["rho"] - 1
+    tiled = {k: np.tile(want[k], (1, nx // P)) for k in want}
+    errs = assert_fields(got, tiled, tol, fields=("drho", "ux", "uy", "sxy", "qx", "qy"),
+                         ctx=prec, atol=ATOL[prec])
+    say("   errors", {k: "%.2e" % v for k, v in errs.items()})
+    g.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp16", 1e-2), ("bf16", 5e-2)])
+@pytest.mark.parametrize("lat", LATS)
+def test_reduced_precision_couette(lat, prec, tol):
+    """Couette from rest, 600 steps; fields of the FP32 / 16-bit storage
+    paths against the FP64 oracle."""
+    say("case reduced", lat, prec)
+    ny = 48
+    kn = 0.05
+    b, t = WALLS[lat]
+    o = oracle_case(lat, 1, ny, O.tau_from_kn(lat, ny, kn), b, t)
+    o.run(600)
+    want = o.moments()
+    g = gpu_case(lat, 2, ny, lbm.lbm_tau_from_kn(lat, ny, kn), b, t, prec=prec)
+    g.step(600)
+    got = g.moments()
+    col = {k: got[k][:, :1] for k in FIELDS}
+    errs = assert_fields(col, want, tol, fields=("ux", "sxy", "qy") + (("T",) if lat == "D3Q121"
+                                                                       else ()), ctx=prec,
+                         atol=ATOL.get(prec, 1e-9))
+    say("   errors", {k: "%.2e" % v for k, v in errs.items()})
+    g.close()
+
+
+def test_checkpoint_resume_is_bitwise():
+    say("case checkpoint")
+    lat = "D3Q121"
+    fields = W.random_fields(6, 20, seed=8, thermal=True)
+    a = gpu_case(lat, 6, 20, 0.9, *WALLS[lat], prec="fp32", fields=fields)
+    a.step(17)
+    state = a.save()
+    a.step(23)
+    want = a.moments()
+    b = gpu_case(lat, 6, 20, 0.9, *WALLS[lat], prec="fp32")
+    b.load(state)
+    assert b.steps_done() == 17
+    b.step(23)
+    got = b.moments()
+    for k in FIELDS:
+        assert np.array_equal(got[k], want[k]), k
+    a.close()
+    b.close()
+
+
+def test_collisionless_limit_closed_form():
+    """tau = inf: steady state is the discrete free-molecular closed form."""
+    say("case collisionless")
+    lat = "D3Q121"
+    g = gpu_case(lat, 1, 12, math.inf, (-0.1, 0, 1.0), (0.1, 0, 1.0))
+    g.step(12000)
+    s = g.field("sxy")
+    assert np.abs(s - (-0.0694789146)).max() < 1e-9
+    g.close()
