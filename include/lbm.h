@@ -172,6 +172,11 @@ void lbm_destroy(lbm_ctx *ctx);
 /* Static string for a status code. */
 const char *lbm_strerror(int status);
 
+/* Name and description of the last HIP runtime error the library saw on the
+ * calling thread ("none" if there was none); valid until the next call on
+ * this thread.  Explains an LBM_EDEVICE / LBM_ENOMEM status. */
+const char *lbm_last_device_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -60,8 +61,8 @@ bool layout(int lattice, lbm_grid g, int prec, Layout* L) {
   if (prec < 0 || prec > 3 || g.nx < 1 || g.ny < 2 * N) return false;
   const long long nodes = (long long)g.nx * g.ny;
   const long long plane = (nodes + 63) / 64 * 64;
-  // element indices of the kernels are 32-bit
-  if ((long long)Q * plane >= (1LL << 31)) return false;
+  // the kernels address a plane set with 32-bit byte offsets
+  if ((unsigned long long)Q * plane * elem_bytes(prec) >= (1ULL << 32)) return false;
   L->plane = plane;
   size_t off = 0;
   L->pop = off;
@@ -87,8 +88,20 @@ int fail(lbm_ctx* c, int st) {
   return st;
 }
 
+// last HIP error seen by the library on this thread (lbm_last_device_error)
+thread_local hipError_t g_last_hip = hipSuccess;
+thread_local char g_last_msg[256];
+
+// true if e is hipSuccess; otherwise records e for lbm_last_device_error
+bool hip_ok(hipError_t e) {
+  if (e == hipSuccess) return true;
+  g_last_hip = e;
+  return false;
+}
+
 int device_status(lbm_ctx* c, hipError_t e) {
   if (e == hipSuccess) return LBM_OK;
+  g_last_hip = e;
   return fail(c, LBM_EDEVICE);
 }
 
@@ -104,6 +117,8 @@ StepArgs make_args(lbm_ctx* c, const void* fin, void* fout, double* mom) {
   a.plane = c->plane;
   a.omega = 1.0 / (c->tau + 0.5);
   a.kfac = std::isinf(c->tau) ? 1.0 : c->tau / (c->tau + 0.5);
+  a.step = uint32_t(c->steps);
+  a.seed = 0x2545f491u;
   return a;
 }
 
@@ -219,7 +234,9 @@ int create_common(lbm_lattice lattice, lbm_grid grid, double tau, const lbm_wall
     c->owns = false;
   } else {
     void* p = nullptr;
-    if (hipMalloc(&p, lay.total) != hipSuccess || !p) {
+    const hipError_t e = hipMalloc(&p, lay.total);
+    if (e != hipSuccess || !p) {
+      g_last_hip = e;
       (void)hipGetLastError();
       delete c;
       return LBM_ENOMEM;
@@ -239,11 +256,9 @@ int create_common(lbm_lattice lattice, lbm_grid grid, double tau, const lbm_wall
   c->result = reinterpret_cast<double*>(c->base + lay.result);
   c->status = LBM_OK;
 
-  int st = LBM_OK;
-  if (hipMemcpyAsync(c->tab, &host_tab, sizeof(Tables), hipMemcpyHostToDevice, c->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
-    st = LBM_EDEVICE;
+  int st = device_status(
+      c, hipMemcpyAsync(c->tab, &host_tab, sizeof(Tables), hipMemcpyHostToDevice, c->stream));
+  if (st == LBM_OK) st = device_status(c, hipStreamSynchronize(c->stream));
   if (st == LBM_OK) st = run_init(c, nullptr);
   if (st != LBM_OK) {
     lbm_destroy(c);
@@ -317,11 +332,11 @@ int lbm_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
   }
   // stage the fields in the output-field area; the init kernel reads a
   // node's inputs before it overwrites them with that node's outputs
-  if (hipMemcpyAsync(c->mom, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
-                     c->stream) != hipSuccess)
+  if (!hip_ok(hipMemcpyAsync(c->mom, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
+                     c->stream)))
     return fail(c, LBM_EDEVICE);
   int st = run_init(c, c->mom);
-  if (st == LBM_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = fail(c, LBM_EDEVICE);
+  if (st == LBM_OK && !hip_ok(hipStreamSynchronize(c->stream))) st = fail(c, LBM_EDEVICE);
   return st;
 }
 
@@ -329,11 +344,11 @@ static constexpr int kTimingChunk = 1024;
 
 static int collect_times(lbm_ctx* c, int used) {
   if (used == 0) return LBM_OK;
-  if (hipEventSynchronize(c->ev[3 * used - 1]) != hipSuccess) return fail(c, LBM_EDEVICE);
+  if (!hip_ok(hipEventSynchronize(c->ev[3 * used - 1]))) return fail(c, LBM_EDEVICE);
   for (int k = 0; k < used; ++k) {
     float w = 0, u = 0;
-    if (hipEventElapsedTime(&w, c->ev[3 * k], c->ev[3 * k + 1]) != hipSuccess ||
-        hipEventElapsedTime(&u, c->ev[3 * k + 1], c->ev[3 * k + 2]) != hipSuccess)
+    if (!hip_ok(hipEventElapsedTime(&w, c->ev[3 * k], c->ev[3 * k + 1])) ||
+        !hip_ok(hipEventElapsedTime(&u, c->ev[3 * k + 1], c->ev[3 * k + 2])))
       return fail(c, LBM_EDEVICE);
     c->t_wall_ms += w;
     c->t_update_ms += u;
@@ -348,16 +363,21 @@ int lbm_step(lbm_ctx* c, int64_t n) {
   if (c->status != LBM_OK) return c->status;
   if (n == 0) return LBM_OK;
   int used = 0;
+  // rows that are a multiple of the block width take the row-tiled update
+  // with the wall sums fused in; other shapes take wall_kernel + update
+  const bool rows = c->nx % kBlock == 0;
   for (int64_t i = 0; i < n; ++i) {
     StepArgs a = make_args(c, c->f[c->cur], c->f[c->cur ^ 1], c->mom);
-    if (c->timing && hipEventRecord(c->ev[3 * used], c->stream) != hipSuccess)
+    a.step = uint32_t(c->steps + i + 1);
+    if (c->timing && !hip_ok(hipEventRecord(c->ev[3 * used], c->stream)))
       return fail(c, LBM_EDEVICE);
-    int st = device_status(c, launch_wall(c->lattice, c->prec, a, c->stream));
-    if (c->timing && hipEventRecord(c->ev[3 * used + 1], c->stream) != hipSuccess)
+    int st = rows ? LBM_OK : device_status(c, launch_wall(c->lattice, c->prec, a, c->stream));
+    if (c->timing && !hip_ok(hipEventRecord(c->ev[3 * used + 1], c->stream)))
       return fail(c, LBM_EDEVICE);
-    if (st == LBM_OK) st = device_status(c, launch_step(c->lattice, c->prec, a, i == n - 1,
-                                                        c->stream));
-    if (c->timing && hipEventRecord(c->ev[3 * used + 2], c->stream) != hipSuccess)
+    if (st == LBM_OK)
+      st = device_status(c, rows ? launch_step_rows(c->lattice, c->prec, a, i == n - 1, c->stream)
+                                 : launch_step(c->lattice, c->prec, a, i == n - 1, c->stream));
+    if (c->timing && !hip_ok(hipEventRecord(c->ev[3 * used + 2], c->stream)))
       return fail(c, LBM_EDEVICE);
     if (st != LBM_OK) return st;
     c->cur ^= 1;
@@ -380,9 +400,9 @@ int lbm_field(lbm_ctx* c, lbm_field_id id, double* host_out) {
   if (!c || !host_out || int(id) < 0 || int(id) >= kFields) return LBM_EINVAL;
   if (c->status != LBM_OK) return c->status;
   const long long nodes = (long long)c->nx * c->ny;
-  if (hipMemcpyAsync(host_out, c->mom + (long long)id * nodes, sizeof(double) * nodes,
-                     hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
+  if (!hip_ok(hipMemcpyAsync(host_out, c->mom + (long long)id * nodes, sizeof(double) * nodes,
+                     hipMemcpyDeviceToHost, c->stream)) ||
+      !hip_ok(hipStreamSynchronize(c->stream)))
     return fail(c, LBM_EDEVICE);
   return LBM_OK;
 }
@@ -402,9 +422,8 @@ int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* T, doub
 
 static int read_result(lbm_ctx* c, double* res) {
   if (c->status != LBM_OK) return c->status;
-  if (hipMemcpyAsync(res, c->result, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
+  if (!hip_ok(hipMemcpyAsync(res, c->result, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream)) ||
+      !hip_ok(hipStreamSynchronize(c->stream)))
     return fail(c, LBM_EDEVICE);
   if (res[3] != 0.0) return fail(c, LBM_ENONFINITE);
   return LBM_OK;
@@ -457,12 +476,12 @@ int lbm_save(lbm_ctx* c, void* host, size_t bytes) {
   std::memcpy(p + 8, &c->window, 8);
   const size_t pop = size_t(c->Q) * c->plane * c->elem;
   const size_t nodes = size_t(c->nx) * c->ny;
-  if (hipMemcpyAsync(p + 16, c->f[c->cur], pop, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-      hipMemcpyAsync(p + 16 + pop, c->mom, sizeof(double) * kFields * nodes,
-                     hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-      hipMemcpyAsync(p + 16 + pop + sizeof(double) * kFields * nodes, c->snap,
-                     sizeof(double) * 4 * nodes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
+  if (!hip_ok(hipMemcpyAsync(p + 16, c->f[c->cur], pop, hipMemcpyDeviceToHost, c->stream)) ||
+      !hip_ok(hipMemcpyAsync(p + 16 + pop, c->mom, sizeof(double) * kFields * nodes,
+                     hipMemcpyDeviceToHost, c->stream)) ||
+      !hip_ok(hipMemcpyAsync(p + 16 + pop + sizeof(double) * kFields * nodes, c->snap,
+                     sizeof(double) * 4 * nodes, hipMemcpyDeviceToHost, c->stream)) ||
+      !hip_ok(hipStreamSynchronize(c->stream)))
     return fail(c, LBM_EDEVICE);
   return LBM_OK;
 }
@@ -477,12 +496,12 @@ int lbm_load(lbm_ctx* c, const void* host, size_t bytes) {
   const size_t pop = size_t(c->Q) * c->plane * c->elem;
   const size_t nodes = size_t(c->nx) * c->ny;
   c->cur = 0;
-  if (hipMemcpyAsync(c->f[0], p + 16, pop, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-      hipMemcpyAsync(c->mom, p + 16 + pop, sizeof(double) * kFields * nodes,
-                     hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-      hipMemcpyAsync(c->snap, p + 16 + pop + sizeof(double) * kFields * nodes,
-                     sizeof(double) * 4 * nodes, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
+  if (!hip_ok(hipMemcpyAsync(c->f[0], p + 16, pop, hipMemcpyHostToDevice, c->stream)) ||
+      !hip_ok(hipMemcpyAsync(c->mom, p + 16 + pop, sizeof(double) * kFields * nodes,
+                     hipMemcpyHostToDevice, c->stream)) ||
+      !hip_ok(hipMemcpyAsync(c->snap, p + 16 + pop + sizeof(double) * kFields * nodes,
+                     sizeof(double) * 4 * nodes, hipMemcpyHostToDevice, c->stream)) ||
+      !hip_ok(hipStreamSynchronize(c->stream)))
     return fail(c, LBM_EDEVICE);
   c->steps = steps;
   c->window = 0;
@@ -495,7 +514,7 @@ int lbm_set_timing(lbm_ctx* c, int enable) {
   if (enable && c->ev.empty()) {
     c->ev.resize(3 * kTimingChunk, nullptr);
     for (auto& e : c->ev)
-      if (hipEventCreate(&e) != hipSuccess) return fail(c, LBM_EDEVICE);
+      if (!hip_ok(hipEventCreate(&e))) return fail(c, LBM_EDEVICE);
   }
   c->timing = enable != 0;
   c->t_update_ms = c->t_wall_ms = 0.0;
@@ -522,6 +541,13 @@ void lbm_destroy(lbm_ctx* c) {
     (void)hipFree(c->base);
   }
   delete c;
+}
+
+const char* lbm_last_device_error(void) {
+  if (g_last_hip == hipSuccess) return "none";
+  std::snprintf(g_last_msg, sizeof(g_last_msg), "%s: %s", hipGetErrorName(g_last_hip),
+                hipGetErrorString(g_last_hip));
+  return g_last_msg;
 }
 
 const char* lbm_strerror(int status) {

@@ -53,49 +53,125 @@ __device__ __forceinline__ R add_scaled(R acc, R v) {
 }
 
 // ---------------------------------------------------------------- codecs --
+// Population planes are accessed through buffer resources (one descriptor
+// per plane set): the per-velocity plane offset q * plane * bytes is a
+// scalar (SGPR) operand and the in-plane node offset a 32-bit vector
+// operand shared by every velocity with the same shift, so the unrolled
+// Q-velocity pulls need no 64-bit address arithmetic.  Accesses beyond the
+// descriptor's size return 0 instead of faulting.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
+  // word 3 = 0x00020000: raw (untyped) dword access on the gfx9 family
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, int(bytes), 0x00020000);
+}
+
 // Storage <-> arithmetic.  Every format holds the deviation g = f - w_q from
 // the rest state, so rounding acts on the (small) deviation, not on f.
 // 16-bit formats hold h = g * S for a per-format power of two S
-// (Tables::dec = 1/S, enc = S) and decode to float.
+// (Tables::dec = 1/S, enc = S) and decode to float.  They round
+// stochastically: a slowly varying population rounded to nearest is rounded
+// the same way every step, and that bias accumulates in the conserved
+// moments over the flow's momentum-diffusion time; unbiased rounding leaves a
+// random walk instead (about 20x smaller errors for FP16 and BF16 in channel
+// flows).  The random bits come from a counter-based hash of (node,
+// velocity, step), so runs are reproducible.
+// Stores are nontemporal (cache policy 2 = nt): a step's output is read only
+// by the next step, after the whole grid has been written, so keeping it in
+// L2 buys nothing and streaming stores sustain a higher HBM write rate.
+constexpr int kStoreNT = 2;
+
+// 32 well-mixed bits from a 32-bit counter ("lowbias32" integer finaliser,
+// C. Wellons).
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
 struct CF64 {
   using S = double;
   using R = double;
-  __device__ static R ld(const S* p, const Tables*) { return *p; }
-  __device__ static void st(S* p, R g, const Tables*) { *p = g; }
+  static constexpr uint32_t B = 8;
+  static constexpr bool kRandom = false;
+  __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  }
+  __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*, uint32_t) {
+    using U2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, g), r, vo, so, kStoreNT);
+  }
 };
 
 struct CF32 {
   using S = float;
   using R = float;
-  __device__ static R ld(const S* p, const Tables*) { return *p; }
-  __device__ static void st(S* p, R g, const Tables*) { *p = g; }
+  static constexpr uint32_t B = 4;
+  static constexpr bool kRandom = false;
+  __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+  }
+  __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*, uint32_t) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(g), r, vo, so, kStoreNT);
+  }
 };
 
 struct CBF16 {
   using S = uint16_t;
   using R = float;
-  __device__ static R ld(const S* p, const Tables* t) {
-    return __uint_as_float(uint32_t(*p) << 16) * t->dec;
+  static constexpr uint32_t B = 2;
+  static constexpr bool kRandom = true;
+  __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables* t) {
+    const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+    return __uint_as_float(h << 16) * t->dec;
   }
-  __device__ static void st(S* p, R g, const Tables* t) {
-    uint32_t u = __float_as_uint(g * t->enc);
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-      *p = uint16_t(0x7fc0);  // keep NaN a NaN
-      return;
-    }
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
-    *p = uint16_t(u >> 16);
+  // Stochastic rounding to the 8-bit significand: add 16 random bits below
+  // the kept ones to the magnitude, truncate.
+  __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables* t,
+                            uint32_t rnd) {
+    const uint32_t u = __float_as_uint(g * t->enc);
+    uint32_t mag = u & 0x7fffffffu;
+    if (mag > 0x7f800000u)
+      mag = 0x7fc00000u;  // keep NaN a NaN
+    else if (mag < 0x7f7f0000u)
+      mag = (mag + (rnd & 0xffffu)) & 0xffff0000u;
+    __builtin_amdgcn_raw_buffer_store_b16(uint16_t(((u & 0x80000000u) | mag) >> 16), r, vo, so,
+                                          kStoreNT);
   }
 };
 
 struct CFP16 {
   using S = _Float16;
   using R = float;
-  __device__ static R ld(const S* p, const Tables* t) { return float(*p) * t->dec; }
-  __device__ static void st(S* p, R g, const Tables* t) {
-    *p = _Float16(g * t->enc);  // v_cvt_f16_f32: round to nearest even
+  static constexpr uint32_t B = 2;
+  static constexpr bool kRandom = true;
+  __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables* t) {
+    const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+    return float(__builtin_bit_cast(_Float16, h)) * t->dec;
+  }
+  // Stochastic rounding to FP16's 10-bit significand in its normal range
+  // [2^-14, 65504]: add 13 random bits below the kept ones to the float's
+  // magnitude and truncate, which leaves a value FP16 holds exactly.  Below
+  // the normal range (rare with the scale S) round to nearest even.
+  __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables* t,
+                            uint32_t rnd) {
+    const uint32_t u = __float_as_uint(g * t->enc);
+    uint32_t mag = u & 0x7fffffffu;
+    if (mag >= 0x38800000u && mag < 0x477fe000u)
+      mag = (mag + (rnd & 0x1fffu)) & 0xffffe000u;
+    const _Float16 h = _Float16(__uint_as_float((u & 0x80000000u) | mag));
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, h), r, vo, so, kStoreNT);
   }
 };
+
+// Descriptor over one plane set of the current step.
+template <class L, class C>
+__device__ __forceinline__ Rsrc plane_set(const void* p, long long plane) {
+  return make_rsrc(p, uint32_t(uint64_t(L::Q) * uint64_t(plane) * C::B));
+}
 
 // ------------------------------------------------------------ equilibrium --
 // Eq. (eq:feq) regrouped as a polynomial in x = c.u whose coefficients
@@ -273,13 +349,19 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-// Columns x - s (periodic) for s = -3..3, valid for any nx >= 1.
-template <int NS>
+// Columns x - s (periodic) for s = -NS..NS.  FAST requires nx >= NS, where
+// one conditional add either way is enough; otherwise any nx >= 1.
+template <int NS, bool FAST>
 __device__ __forceinline__ void wrapped_columns(int x, int nx, int (&xw)[2 * NS + 1]) {
   for (int s = -NS; s <= NS; ++s) {
     int c = x - s;
-    while (c < 0) c += nx;
-    while (c >= nx) c -= nx;
+    if constexpr (FAST) {
+      c += c < 0 ? nx : 0;
+      c -= c >= nx ? nx : 0;
+    } else {
+      while (c < 0) c += nx;
+      while (c >= nx) c -= nx;
+    }
     xw[s + NS] = c;
   }
 }
@@ -330,8 +412,7 @@ struct WallTerms {
 };
 
 template <class L, class C, bool TOP>
-__device__ __forceinline__ double ghost_mass(const typename C::S* __restrict__ fin,
-                                             const StepArgs& a, int xp, int lane) {
+__device__ __forceinline__ double ghost_mass(Rsrc fin, const StepArgs& a, int xp, int lane) {
   using W = WallTerms<L>;
   double acc = 0.0;
   auto body = [&](auto tc) {
@@ -342,9 +423,8 @@ __device__ __forceinline__ double ghost_mass(const typename C::S* __restrict__ f
       while (xs < 0) xs += a.nx;
       while (xs >= a.nx) xs -= a.nx;
       const int row = TOP ? a.ny - 1 - T.j : T.j;
-      const uint32_t idx = uint32_t(T.q) * uint32_t(a.plane) + uint32_t(row) * uint32_t(a.nx) +
-                           uint32_t(xs);
-      acc += double(C::ld(fin + idx, a.tab));
+      acc += double(C::ld(fin, (uint32_t(row) * uint32_t(a.nx) + uint32_t(xs)) * C::B,
+                          uint32_t(T.q) * uint32_t(a.plane) * C::B, a.tab));
     }
   };
   static_for<0, W::NT>(body);
@@ -358,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void wall_kernel(StepArgs a) {
   const int wave = int((blockIdx.x * kBlock + threadIdx.x) >> 6);
   const int lane = int(threadIdx.x & 63);
   if (wave >= 2 * a.nx) return;  // wave-uniform
-  const auto* fin = static_cast<const typename C::S*>(a.fin);
+  const Rsrc fin = plane_set<L, C>(a.fin, a.plane);
   const bool top = wave >= a.nx;
   const int xp = top ? wave - a.nx : wave;
   double M;
@@ -374,40 +454,39 @@ __global__ __launch_bounds__(kBlock) void wall_kernel(StepArgs a) {
 }
 
 // ------------------------------------------------------------- the step --
-template <class L, class C>
-__device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a, int x,
-                                     int y) {
+// Pull of one node: f~_q(x, y) = f*_q(x - e_x, y - e_y), or, when the source
+// row lies in a ghost layer, the value the wall re-emits there:
+// g^eq_q(u_w, T_w) * (pooled mass / D) of the source's ghost column (read
+// through ratio(wall, q)).  Returns deviations from w_q.
+template <class L, class C, class Ratio>
+__device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a, int y,
+                                     const int (&xw)[2 * max_ex<L>() + 1], Ratio&& ratio) {
   using R = typename C::R;
-  using S = typename C::S;
   constexpr int NS = max_ex<L>();
-  const auto* __restrict__ fin = static_cast<const S*>(a.fin);
-  int xw[2 * NS + 1];
-  wrapped_columns<NS>(x, a.nx, xw);
-  const uint32_t plane = uint32_t(a.plane);
+  const Rsrc fin = plane_set<L, C>(a.fin, a.plane);
   const uint32_t nx = uint32_t(a.nx);
+  const uint32_t pb = uint32_t(a.plane) * C::B;  // bytes per plane
   if (y >= L::N && y < a.ny - L::N) {
     auto body = [&](auto qc) {
       constexpr int q = decltype(qc)::value;
       constexpr int ex = L::E[q][0], ey = L::E[q][1];
-      const uint32_t idx = uint32_t(q) * plane + uint32_t(y - ey) * nx + uint32_t(xw[ex + NS]);
-      f[q] = C::ld(fin + idx, a.tab);
+      f[q] = C::ld(fin, (uint32_t(y - ey) * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(q) * pb,
+                   a.tab);
     };
     static_for<0, L::Q>(body);
   } else {
-    const double* rb = a.ratio;
-    const double* rt = a.ratio + a.nx;
     auto body = [&](auto qc) {
       constexpr int q = decltype(qc)::value;
       constexpr int ex = L::E[q][0], ey = L::E[q][1];
       const int ys = y - ey;
       if (ey > 0 && ys < 0) {
         // re-emitted by the bottom wall: f = g^eq(u_b, T_b) M / D
-        f[q] = R(a.tab->gb[q] * rb[xw[ex + NS]] - L::W[q]);
+        f[q] = R(a.tab->gb[q] * ratio(0, ex) - L::W[q]);
       } else if (ey < 0 && ys >= a.ny) {
-        f[q] = R(a.tab->gt[q] * rt[xw[ex + NS]] - L::W[q]);  // top wall
+        f[q] = R(a.tab->gt[q] * ratio(1, ex) - L::W[q]);  // top wall
       } else {
-        const uint32_t idx = uint32_t(q) * plane + uint32_t(ys) * nx + uint32_t(xw[ex + NS]);
-        f[q] = C::ld(fin + idx, a.tab);
+        f[q] = C::ld(fin, (uint32_t(ys) * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(q) * pb,
+                     a.tab);
       }
     };
     static_for<0, L::Q>(body);
@@ -417,28 +496,97 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
 template <class L, class C>
 __device__ __forceinline__ void store(const typename C::R (&f)[L::Q], const StepArgs& a,
                                       uint32_t n) {
-  auto* __restrict__ fout = static_cast<typename C::S*>(a.fout);
-  const uint32_t plane = uint32_t(a.plane);
+  const Rsrc fout = plane_set<L, C>(a.fout, a.plane);
+  const uint32_t pb = uint32_t(a.plane) * C::B;
+  // counter for the stochastic rounding of 16-bit formats: (node, q, step)
+  const uint32_t key = C::kRandom ? mix32(a.step * 0x9e3779b9u + a.seed) ^ (n * uint32_t(L::Q)) : 0u;
   auto body = [&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    C::st(fout + uint32_t(q) * plane + n, f[q], a.tab);
+    const uint32_t rnd = C::kRandom ? mix32(key + uint32_t(q) * 0x85ebca77u) : 0u;
+    C::st(fout, n * C::B, uint32_t(q) * pb, f[q], a.tab, rnd);
   };
   static_for<0, L::Q>(body);
 }
 
+// Pooled incoming mass of one ghost column, summed serially in a fixed order
+// (deviations only; the rest-state part is added by the caller).
+template <class L, class C, bool TOP>
+__device__ __forceinline__ double ghost_column_deviation(const StepArgs& a, int xp) {
+  using W = WallTerms<L>;
+  const Rsrc fin = plane_set<L, C>(a.fin, a.plane);
+  double acc = 0.0;
+  auto body = [&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    constexpr auto T = TOP ? W::top().t[t] : W::bottom().t[t];
+    int xs = xp - T.ex;
+    xs += xs < 0 ? a.nx : 0;
+    xs -= xs >= a.nx ? a.nx : 0;
+    const int row = TOP ? a.ny - 1 - T.j : T.j;
+    acc += double(C::ld(fin, (uint32_t(row) * uint32_t(a.nx) + uint32_t(xs)) * C::B,
+                        uint32_t(T.q) * uint32_t(a.plane) * C::B, a.tab));
+  };
+  static_for<0, W::NT>(body);
+  return acc;
+}
+
+// Any grid shape: one thread per node on a linear node index; the ghost
+// ratios come from wall_kernel, launched before.
 template <class L, class C, bool MOM>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
   using R = typename C::R;
+  constexpr int NS = max_ex<L>();
   const long long nodes = (long long)a.nx * a.ny;
   const long long n = (long long)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (n >= nodes) return;
   const int y = int(n / a.nx);
   const int x = int(n - (long long)y * a.nx);
+  int xw[2 * NS + 1];
+  wrapped_columns<NS, false>(x, a.nx, xw);
   R f[L::Q];
-  pull<L, C>(f, a, x, y);
+  pull<L, C>(f, a, y, xw,
+             [&](int wall, int ex) { return a.ratio[wall * a.nx + xw[ex + NS]]; });
   if constexpr (MOM) write_fields<L, R>(f, a.kfac, a.mom, nodes, n);
   relax<L, R>(f, R(a.omega));
   store<L, C>(f, a, uint32_t(n));
+}
+
+// Rows that are a multiple of kBlock wide: each block owns kBlock
+// consecutive nodes of one row (x0 .. x0+kBlock-1), so the row index is
+// wave-uniform and no integer division per thread is needed.  Blocks of the
+// N rows next to a wall first compute the pooled ghost-column ratios of the
+// kBlock + 2 NS columns their pulls can reach into LDS (fusing the wall sums
+// into the update: no separate launch, no global round trip).
+template <class L, class C, bool MOM>
+__global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
+  using R = typename C::R;
+  constexpr int NS = max_ex<L>();
+  __shared__ double ratio_s[kBlock + 2 * NS];
+  const int bpr = a.nx / kBlock;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int y = b / bpr;
+  const int x0 = (b - y * bpr) * kBlock;
+  const int x = x0 + int(threadIdx.x);
+  int xw[2 * NS + 1];
+  wrapped_columns<NS, true>(x, a.nx, xw);
+  const bool bottom = y < L::N, top = y >= a.ny - L::N;  // block-uniform
+  if (bottom || top) {
+    for (int s = threadIdx.x; s < kBlock + 2 * NS; s += kBlock) {
+      int c = x0 - NS + s;
+      c += c < 0 ? a.nx : 0;
+      c -= c >= a.nx ? a.nx : 0;
+      ratio_s[s] = top ? (a.tab->Wt + ghost_column_deviation<L, C, true>(a, c)) / a.tab->Dt
+                       : (a.tab->Wb + ghost_column_deviation<L, C, false>(a, c)) / a.tab->Db;
+    }
+    __syncthreads();
+  }
+  R f[L::Q];
+  pull<L, C>(f, a, y, xw,
+             [&](int, int ex) { return ratio_s[int(threadIdx.x) - ex + NS]; });
+  const long long nodes = (long long)a.nx * a.ny;
+  const uint32_t n = uint32_t(y) * uint32_t(a.nx) + uint32_t(x);
+  if constexpr (MOM) write_fields<L, R>(f, a.kfac, a.mom, nodes, n);
+  relax<L, R>(f, R(a.omega));
+  store<L, C>(f, a, n);
 }
 
 // f~(0) = f^eq(rho0, u0, T0); writes the output fields of f~(0) and stores
@@ -473,6 +621,11 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double* 
   store<L, C>(f, a, uint32_t(n));
 }
 
+// hipGetLastError reports the last error of any HIP call on this thread,
+// including calls made by other libraries in the process; clear it before a
+// launch so the check after the launch sees only the launch itself.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
 inline unsigned grid_for(long long threads) {
   return unsigned((threads + kBlock - 1) / kBlock);
 }
@@ -484,12 +637,14 @@ template <class L, class C>
 struct SetOps {
   static hipError_t wall(const StepArgs& a, hipStream_t s);
   static hipError_t step(const StepArgs& a, bool moments, hipStream_t s);
+  static hipError_t step_rows(const StepArgs& a, bool moments, hipStream_t s);
   static hipError_t init(const StepArgs& a, const double* fields, hipStream_t s);
 };
 
 #ifdef LBM_DEFINE_SET_OPS
 template <class L, class C>
 hipError_t SetOps<L, C>::wall(const StepArgs& a, hipStream_t s) {
+  clear_stale_error();
   hipLaunchKernelGGL((wall_kernel<L, C>), dim3(grid_for(2LL * a.nx * 64)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
@@ -497,6 +652,7 @@ hipError_t SetOps<L, C>::wall(const StepArgs& a, hipStream_t s) {
 template <class L, class C>
 hipError_t SetOps<L, C>::step(const StepArgs& a, bool moments, hipStream_t s) {
   const dim3 grid(grid_for((long long)a.nx * a.ny));
+  clear_stale_error();
   if (moments)
     hipLaunchKernelGGL((step_kernel<L, C, true>), grid, dim3(kBlock), 0, s, a);
   else
@@ -505,7 +661,19 @@ hipError_t SetOps<L, C>::step(const StepArgs& a, bool moments, hipStream_t s) {
 }
 
 template <class L, class C>
+hipError_t SetOps<L, C>::step_rows(const StepArgs& a, bool moments, hipStream_t s) {
+  const dim3 grid(unsigned(a.nx / kBlock) * unsigned(a.ny));
+  clear_stale_error();
+  if (moments)
+    hipLaunchKernelGGL((step_rows_kernel<L, C, true>), grid, dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((step_rows_kernel<L, C, false>), grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class L, class C>
 hipError_t SetOps<L, C>::init(const StepArgs& a, const double* fields, hipStream_t s) {
+  clear_stale_error();
   hipLaunchKernelGGL((init_kernel<L, C>), dim3(grid_for((long long)a.nx * a.ny)), dim3(kBlock),
                      0, s, a, fields);
   return hipGetLastError();

@@ -94,6 +94,14 @@ hipError_t launch_step(int lattice, int prec, const StepArgs& a, bool moments, h
   });
 }
 
+hipError_t launch_step_rows(int lattice, int prec, const StepArgs& a, bool moments,
+                            hipStream_t s) {
+  return by_set(lattice, [&](auto lat) {
+    return by_prec<decltype(lat)>(
+        prec, [&](auto ops) { return decltype(ops)::step_rows(a, moments, s); });
+  });
+}
+
 hipError_t launch_init(int lattice, int prec, const StepArgs& a, const double* fields,
                        hipStream_t s) {
   return by_set(lattice, [&](auto lat) {
@@ -103,6 +111,7 @@ hipError_t launch_init(int lattice, int prec, const StepArgs& a, const double* f
 }
 
 hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s) {
+  dev::clear_stale_error();
   hipLaunchKernelGGL(dev::reduce_partial, dim3(kReduceBlocks), dim3(kBlock), 0, s, r);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -40,6 +40,8 @@ struct StepArgs {
   long long plane;      // elements between population planes
   double omega;         // 1 / (tau + 1/2)
   double kfac;          // tau / (tau + 1/2): f~ -> f conversion of sigma, q
+  uint32_t step;        // index of the step being produced (rounding counter)
+  uint32_t seed;        // per-context rounding seed
 };
 
 struct ReduceArgs {
@@ -54,6 +56,10 @@ struct ReduceArgs {
 hipError_t launch_wall(int lattice, int prec, const StepArgs& a, hipStream_t s);
 hipError_t launch_step(int lattice, int prec, const StepArgs& a, bool moments,
                        hipStream_t s);
+// Same update for nx a multiple of kBlock, with the wall sums fused in: no
+// launch_wall needed before it.
+hipError_t launch_step_rows(int lattice, int prec, const StepArgs& a, bool moments,
+                            hipStream_t s);
 // f~ = f^eq(fields) -> collide -> fout; also writes the output fields.
 // fields: rho, ux, uy, uz, T (5 x nodes doubles, may alias a.mom).
 hipError_t launch_init(int lattice, int prec, const StepArgs& a,

@@ -36,6 +36,8 @@ class LbmError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
         msg = lbm_strerror(status) if _lib is not None else str(status)
+        if _lib is not None and status in (LBM_EDEVICE, LBM_ENOMEM):
+            msg += " [%s]" % _lib.lbm_last_device_error().decode()
         super().__init__("%s: %s (status %d)" % (what, msg, status))
 
 
@@ -60,6 +62,15 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("liblbm.so is not built (%s); run `python -m "
                            "paper_1209_5201_amd.build`" % LIB_PATH)
+    # torch ships its own HIP runtime under the same soname
+    # (libamdhip64.so.7).  Loading torch first makes the library bind to that
+    # runtime, so the process has one HIP runtime, torch's memory and streams
+    # are native handles, and devices are visible to both.  (Loading the
+    # library first would pull in a second runtime that sees no device.)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "lbm_lattice_info": (ctypes.c_int, [ctypes.c_int, _ip, _ip, _ip, _ip, _dp, _ip, _dp]),
@@ -87,6 +98,7 @@ def _load():
                                            ctypes.POINTER(ctypes.c_int64)]),
         "lbm_destroy": (None, [_vp]),
         "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "lbm_last_device_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -101,7 +113,8 @@ def exported_symbols():
     return ["lbm_lattice_info", "lbm_tau_from_kn", "lbm_required_bytes", "lbm_create",
             "lbm_create_in", "lbm_init", "lbm_step", "lbm_field", "lbm_moments",
             "lbm_residual", "lbm_mass", "lbm_steps_done", "lbm_state_bytes", "lbm_save",
-            "lbm_load", "lbm_set_timing", "lbm_kernel_time", "lbm_destroy", "lbm_strerror"]
+            "lbm_load", "lbm_set_timing", "lbm_kernel_time", "lbm_destroy", "lbm_strerror",
+            "lbm_last_device_error"]
 
 
 def _check(st: int, what: str):

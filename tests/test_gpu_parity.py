@@ -94,6 +94,23 @@ def test_fp64_random_start_several_tiles_ragged(lat):
     g.close()
 
 
+@pytest.mark.parametrize("lat", LATS)
+def test_fp64_row_tiled_path_with_fused_wall_sums(lat):
+    """nx a multiple of the block width takes the row-tiled update whose wall
+    rows compute the ghost-column sums in LDS (including the periodic wrap
+    at the row ends)."""
+    nx, ny = 512, 12
+    say("case fp64 rows", lat, nx, ny)
+    fields = W.random_fields(nx, ny, seed=5, thermal=(lat == "D3Q121"))
+    g = gpu_case(lat, nx, ny, 0.7, *WALLS[lat], fields=fields)
+    o = oracle_case(lat, nx, ny, 0.7, *WALLS[lat], fields=fields)
+    for t in (1, 24):
+        g.step(t)
+        o.run(t)
+        assert_fields(g.moments(), o.moments(), 1e-12, ctx="t=%d" % o.t)
+    g.close()
+
+
 @pytest.mark.parametrize("lat", ["D2Q16", "D2Q17"])
 def test_c1_isothermal_couette_fp64(lat):
     c = W.C1
@@ -207,26 +224,110 @@ def test_c3_full_size_launch_against_tiled_oracle(prec, tol):
     g.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp16", 1e-2), ("bf16", 5e-2)])
+def xavg(fields):
+    """Channel profiles: x-averages of the (x-invariant) fields."""
+    return {k: v.mean(axis=1, keepdims=True) for k, v in fields.items()}
+
+
+# Bars for x-averaged profiles of a channel started from rest (the 16-bit
+# formats round stochastically; the averages remove the per-node rounding
+# noise, not the accumulated bias a deterministic rounding would leave).
+REDUCED_TOL = {"fp32": 1e-5, "fp16": 1e-3, "bf16": 1e-2}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("lat", LATS)
-def test_reduced_precision_couette(lat, prec, tol):
-    """Couette from rest, 600 steps; fields of the FP32 / 16-bit storage
-    paths against the FP64 oracle."""
+def test_reduced_precision_couette_profiles(lat, prec):
+    """Couette from rest, 600 steps, 256 columns; x-averaged profiles of the
+    FP32 / 16-bit storage paths against the FP64 oracle (one column)."""
     say("case reduced", lat, prec)
-    ny = 48
-    kn = 0.05
+    ny, kn = 48, 0.05
     b, t = WALLS[lat]
     o = oracle_case(lat, 1, ny, O.tau_from_kn(lat, ny, kn), b, t)
     o.run(600)
     want = o.moments()
-    g = gpu_case(lat, 2, ny, lbm.lbm_tau_from_kn(lat, ny, kn), b, t, prec=prec)
+    g = gpu_case(lat, 256, ny, lbm.lbm_tau_from_kn(lat, ny, kn), b, t, prec=prec)
     g.step(600)
-    got = g.moments()
-    col = {k: got[k][:, :1] for k in FIELDS}
-    errs = assert_fields(col, want, tol, fields=("ux", "sxy", "qy") + (("T",) if lat == "D3Q121"
-                                                                       else ()), ctx=prec,
+    got = xavg(g.moments())
+    fields = ("ux", "sxy") + (("T", "qy") if lat == "D3Q121" else ())
+    errs = assert_fields(got, want, REDUCED_TOL[prec], fields=fields, ctx=prec,
                          atol=ATOL.get(prec, 1e-9))
     say("   errors", {k: "%.2e" % v for k, v in errs.items()})
+    g.close()
+
+
+def channel_results(m, top_wall_u, bottom_wall_T):
+    """The per-result quantities reported for a channel run: x-averaged
+    profiles of u_x, T, sigma_xy and q_y, and the slip and temperature jump
+    read off least-squares fits over the central half of the channel (linear
+    for u, quadratic for T), extrapolated to the walls at Y = 1 and Y = 0."""
+    p = xavg(m)
+    ny = p["ux"].shape[0]
+    Y = (np.arange(ny) + 0.5) / ny
+    mid = slice(ny // 4, 3 * ny // 4)
+    ufit = np.polyfit(Y[mid], p["ux"][mid, 0], 1)
+    Tfit = np.polyfit(Y[mid], p["T"][mid, 0], 2)
+    return {"u": p["ux"][:, 0], "T": p["T"][:, 0], "sxy": p["sxy"][:, 0], "qy": p["qy"][:, 0],
+            "slip": top_wall_u - np.polyval(ufit, 1.0),
+            "jump": np.polyval(Tfit, 0.0) - bottom_wall_T}
+
+
+def result_errors(got, want, atol):
+    """Relative error of each result after removing an absolute rounding
+    floor atol (profiles: relative to their largest magnitude; T: relative
+    to the temperature rise above the wall)."""
+    def rel(diff, scale):
+        return max(diff - atol, 0.0) / scale
+    out = {}
+    for k in ("u", "sxy", "qy"):
+        out[k] = rel(np.abs(got[k] - want[k]).max(), np.abs(want[k]).max())
+    out["T"] = rel(np.abs(got["T"] - want["T"]).max(), np.abs(want["T"] - 1.0).max())
+    for k in ("slip", "jump"):
+        out[k] = rel(abs(got[k] - want[k]), abs(want[k]))
+    return out
+
+
+@pytest.fixture(scope="module")
+def c5_reference():
+    c = W.C5
+    lat = c["lattice"]
+    say("C5 oracle: %s 1 x %d, %d steps" % (lat, c["ny"], c["steps"]))
+    o = O.OracleCase(lat, 1, c["ny"], O.tau_from_kn(lat, c["ny"], c["kn"]), c["bottom"],
+                     c["top"])
+    o.run(c["steps"])
+    return channel_results(o.moments(), c["top"][0], c["bottom"][2])
+
+
+# Bars per storage format and result for the C5 run.  With both walls at
+# T = 1 the heat flux is the small viscous-heating flux of an early
+# transient; its per-node rounding noise survives the x-average more than
+# that of the other results, hence the wider q_y bars of the 16-bit formats.
+C5_TOL = {"fp64": dict(rest=1e-12), "fp32": dict(rest=1e-5),
+          "fp16": dict(rest=1e-3, qy=5e-3), "bf16": dict(rest=1e-2, qy=5e-2)}
+C5_ATOL = {"fp64": 1e-15, "fp32": 1e-9, "fp16": 0.0, "bf16": 0.0}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
+def test_c5_full_size_results(c5_reference, prec):
+    """D3Q121 1024 x 1024, walls -0.1 / +0.1 at T = 1, Kn = 0.05, rest start,
+    5000 steps.  x-invariant, so the oracle runs one column; every reported
+    result of the x-averaged GPU fields is compared with it."""
+    c = W.C5
+    lat = c["lattice"]
+    say("case C5", prec)
+    g = lbm.Channel(lat, c["nx"], c["ny"], lbm.lbm_tau_from_kn(lat, c["ny"], c["kn"]),
+                    c["bottom"], c["top"], prec=prec)
+    g.step(c["steps"])
+    m = g.moments()
+    if prec in ("fp64", "fp32"):
+        for k in ("ux", "T", "sxy", "qy"):
+            assert np.abs(m[k] - m[k][:, :1]).max() == 0.0, k   # exactly x-invariant
+    errs = result_errors(channel_results(m, c["top"][0], c["bottom"][2]), c5_reference,
+                         C5_ATOL[prec])
+    say("   errors", {k: "%.2e" % v for k, v in errs.items()})
+    tol = C5_TOL[prec]
+    bad = {k: v for k, v in errs.items() if not v <= tol.get(k, tol["rest"])}
+    assert not bad, (prec, bad)
     g.close()
 
 
