@@ -9,6 +9,12 @@ rows, pull, collide, store; the output fields, mass and residual are
 refreshed after the last step of the timed call).  Inputs are resident in
 HBM before timing starts.
 
+Also measured (the "serving" object): the Couette serving stream - 1024
+seeded requests over the three velocity sets, Ny in [16, 512], Kn log-uniform
+in [0.01, 0.5], each run to a residual rate of 1e-8 in FP32 - as saturated
+solves/s and, at 100 Poisson arrivals per second, p50/p99 time-to-solution,
+beside the same requests solved one at a time in FP64.
+
 Prints one JSON line: MLUPS (million lattice-node updates per second), the
 HBM roofline of the fused update kernel (algorithmic bytes 2*Q*4 per node,
 kernel time from HIP events around every launch of a second pass of the
@@ -118,6 +124,36 @@ def cpu_baseline(cfg, nsteps: int):
                       % (cfg["lattice"], cfg["nx"], cfg["ny"], nsteps, dt)}
 
 
+def serving(n_requests: int, rate: float, baseline_cases: int):
+    """Couette serving stream (FP32, residual 1e-8): saturated throughput
+    with every request queued at t = 0, then latency at a fixed Poisson
+    arrival rate; the same first `baseline_cases` requests solved one at a
+    time in FP64 as the baseline."""
+    from paper_1209_5201_amd import serve
+    from paper_1209_5201_amd import workloads as W
+    reqs = W.serving_requests(n=n_requests, seed=1, rate=rate)
+    sat = serve.Server(prec="fp32", window=100, tol=1e-8, keep_profiles=False).run(
+        reqs, realtime=False)
+    live = serve.Server(prec="fp32", window=100, tol=1e-8, keep_profiles=False).run(
+        reqs, realtime=True)
+    base = serve.one_at_a_time(reqs[:baseline_cases], prec="fp64")
+    same = serve.Server(prec="fp32", window=100, tol=1e-8, keep_profiles=False).run(
+        reqs[:baseline_cases], realtime=False)
+
+    def r(x):
+        return round(x, 4)
+    return {"requests": n_requests, "precision": "fp32", "tolerance": 1e-8,
+            "saturated_solves_per_s": r(sat["solves_per_s"]),
+            "saturated_converged": sat["converged"],
+            "arrival_rate_per_s": rate,
+            "solves_per_s": r(live["solves_per_s"]),
+            "p50_time_to_solution_s": r(live["p50_s"]), "p99_time_to_solution_s": r(live["p99_s"]),
+            "p50_service_s": r(live["p50_service_s"]), "p99_service_s": r(live["p99_service_s"]),
+            "baseline": {"kind": "one at a time, FP64, same library", "requests": baseline_cases,
+                         "solves_per_s": r(base["solves_per_s"]),
+                         "batched_fp32_same_requests_solves_per_s": r(same["solves_per_s"])}}
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
     """Device-to-device copy rate (read + write bytes / time) as a practical
     HBM ceiling, measured in the same run."""
@@ -142,6 +178,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--serving-requests", type=int, default=1024)
+    ap.add_argument("--serving-rate", type=float, default=100.0)
+    ap.add_argument("--serving-baseline", type=int, default=16)
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(args.traffic_from[0], args.traffic_from[1],
@@ -221,6 +261,9 @@ def main():
         "mass_after": mass,
     }
     ch.close()
+    if not args.no_serving:
+        line["serving"] = serving(args.serving_requests, args.serving_rate,
+                                  args.serving_baseline)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
     print(json.dumps(line), flush=True)

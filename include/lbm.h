@@ -157,6 +157,31 @@ size_t lbm_state_bytes(lbm_ctx *ctx);
 int lbm_save(lbm_ctx *ctx, void *host, size_t bytes);
 int lbm_load(lbm_ctx *ctx, const void *host, size_t bytes);
 
+/* Serving: advance several contexts by k_steps in one persistent launch per
+ * storage format present (one workgroup per context; the whole k-step
+ * window runs inside the launch), then refresh each context's fields, mass
+ * and residual exactly as lbm_step(ctx, k_steps) would.  A context's result
+ * does not depend on which other contexts share the batch.  All contexts
+ * must use the same HIP stream and device and appear once; nx <= 64
+ * (LBM_EUNSUPPORTED otherwise: use lbm_step for wide grids).
+ * residuals_out (may be NULL): n_ctx residuals as lbm_residual reports them,
+ * NaN for a context whose fields became non-finite.  Synchronizes the stream.
+ * Not thread-safe against concurrent lbm_batch_step calls on other threads
+ * for the same contexts. */
+int lbm_batch_step(lbm_ctx *const *ctxs, int n_ctx, int64_t k_steps, double *residuals_out);
+
+/* Serving with convergence inside the launch: context i advances in windows
+ * of `window` steps, at most budgets[i] steps (rounded down to a multiple of
+ * the window; >= window), and stops after the first window whose residual
+ * (as lbm_residual defines it, over that window) is below tol.  A context's
+ * stopping step depends only on its own data, not on the batch or on its
+ * budget.  Outputs (each may be NULL): the residual of each context's last
+ * window (NaN: non-finite), the steps it advanced, and its state (1
+ * converged, 0 budget used up, -1 non-finite fields).  Same conventions as
+ * lbm_batch_step. */
+int lbm_batch_run(lbm_ctx *const *ctxs, int n_ctx, const int64_t *budgets, int64_t window,
+                  double tol, double *residuals_out, int64_t *steps_out, int *state_out);
+
 /* Kernel timing with HIP events (profiling aid).  While enabled, lbm_step
  * brackets every launch of the wall-sum kernel and of the fused update kernel
  * with events on the context stream and accumulates their durations; the

@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <climits>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -507,6 +509,101 @@ int lbm_load(lbm_ctx* c, const void* host, size_t bytes) {
   c->window = 0;
   (void)window;
   return LBM_OK;
+}
+
+// Device scratch of lbm_batch_step (case descriptors + outputs), grown on
+// demand and kept for the life of the process; guarded by a mutex.
+static std::mutex g_batch_mu;
+static char* g_batch_dev = nullptr;
+static size_t g_batch_cap = 0;
+
+int lbm_batch_run(lbm_ctx* const* ctxs, int n_ctx, const int64_t* budgets, int64_t window,
+                  double tol, double* residuals_out, int64_t* steps_out, int* state_out) {
+  if (!ctxs || n_ctx <= 0 || !budgets || window <= 0 || window > INT_MAX) return LBM_EINVAL;
+  if (!ctxs[0]) return LBM_EINVAL;
+  const hipStream_t stream = ctxs[0]->stream;
+  for (int i = 0; i < n_ctx; ++i) {
+    lbm_ctx* c = ctxs[i];
+    if (!c || c->stream != stream) return LBM_EINVAL;
+    if (c->status != LBM_OK) return c->status;
+    if (c->nx > kBatchMaxNx) return LBM_EUNSUPPORTED;
+    if (budgets[i] < window || budgets[i] > INT_MAX) return LBM_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return LBM_EINVAL;  // one context twice would race
+  }
+  // group the cases by storage format: one launch per format present
+  std::vector<CaseDesc> desc(n_ctx);
+  std::vector<int> pos(n_ctx);
+  int start[5] = {0, 0, 0, 0, 0};
+  int m = 0;
+  for (int p = 0; p < 4; ++p) {
+    start[p] = m;
+    for (int i = 0; i < n_ctx; ++i) {
+      lbm_ctx* c = ctxs[i];
+      if (c->prec != p) continue;
+      CaseDesc& d = desc[m];
+      d.a = make_args(c, nullptr, nullptr, c->mom);
+      d.f[0] = c->f[0];
+      d.f[1] = c->f[1];
+      d.cur = c->cur;
+      d.snap = c->snap;
+      d.result = c->result;
+      d.uref = c->uref;
+      d.tol = tol;
+      d.lattice = c->lattice;
+      d.window = int(window);
+      d.budget = int(budgets[i] / window * window);
+      pos[i] = m++;
+    }
+  }
+  start[4] = m;
+  const size_t desc_bytes = align256(sizeof(CaseDesc) * size_t(n_ctx));
+  const size_t need = desc_bytes + sizeof(CaseOut) * size_t(n_ctx);
+  std::vector<CaseOut> out(n_ctx);
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  if (need > g_batch_cap) {
+    if (g_batch_dev) (void)hipFree(g_batch_dev);
+    g_batch_dev = nullptr;
+    g_batch_cap = 0;
+    void* p = nullptr;
+    if (!hip_ok(hipMalloc(&p, need))) return LBM_ENOMEM;
+    g_batch_dev = static_cast<char*>(p);
+    g_batch_cap = need;
+  }
+  CaseDesc* ddesc = reinterpret_cast<CaseDesc*>(g_batch_dev);
+  CaseOut* dout = reinterpret_cast<CaseOut*>(g_batch_dev + desc_bytes);
+  if (!hip_ok(hipMemcpyAsync(ddesc, desc.data(), sizeof(CaseDesc) * size_t(n_ctx),
+                             hipMemcpyHostToDevice, stream)))
+    return LBM_EDEVICE;
+  for (int p = 0; p < 4; ++p) {
+    const int cnt = start[p + 1] - start[p];
+    if (cnt == 0) continue;
+    if (!hip_ok(launch_batch(p, ddesc + start[p], cnt, dout + start[p], stream)))
+      return LBM_EDEVICE;
+  }
+  if (!hip_ok(hipMemcpyAsync(out.data(), dout, sizeof(CaseOut) * out.size(),
+                             hipMemcpyDeviceToHost, stream)) ||
+      !hip_ok(hipStreamSynchronize(stream)))
+    return LBM_EDEVICE;
+  for (int i = 0; i < n_ctx; ++i) {
+    lbm_ctx* c = ctxs[i];
+    const CaseOut& o = out[pos[i]];
+    const int64_t done = int64_t(o.steps);
+    c->cur ^= int(done & 1);
+    c->steps += done;
+    c->window = window;
+    if (residuals_out) residuals_out[i] = o.residual;
+    if (steps_out) steps_out[i] = done;
+    if (state_out) state_out[i] = int(o.state);
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_ctx* const* ctxs, int n_ctx, int64_t k_steps, double* residuals_out) {
+  if (!ctxs || n_ctx <= 0 || k_steps <= 0) return LBM_EINVAL;
+  std::vector<int64_t> budgets(n_ctx, k_steps);
+  return lbm_batch_run(ctxs, n_ctx, budgets.data(), k_steps, -1.0, residuals_out, nullptr,
+                       nullptr);
 }
 
 int lbm_set_timing(lbm_ctx* c, int enable) {

@@ -76,10 +76,13 @@ __device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
 // random walk instead (about 20x smaller errors for FP16 and BF16 in channel
 // flows).  The random bits come from a counter-based hash of (node,
 // velocity, step), so runs are reproducible.
-// Stores are nontemporal (cache policy 2 = nt): a step's output is read only
-// by the next step, after the whole grid has been written, so keeping it in
-// L2 buys nothing and streaming stores sustain a higher HBM write rate.
+// Stores of the grid-wide update are nontemporal (cache policy 2 = nt): a
+// step's output is read only by the next step, after the whole grid has been
+// written, so keeping it in L2 buys nothing and streaming stores sustain a
+// higher HBM write rate.  The persistent small-case kernel stores with the
+// default policy (0): its next step reads the data back from cache.
 constexpr int kStoreNT = 2;
+constexpr int kStoreCached = 0;
 
 // 32 well-mixed bits from a 32-bit counter ("lowbias32" integer finaliser,
 // C. Wellons).
@@ -100,9 +103,10 @@ struct CF64 {
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
   }
+  template <int POL>
   __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*, uint32_t) {
     using U2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, g), r, vo, so, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, g), r, vo, so, POL);
   }
 };
 
@@ -114,8 +118,9 @@ struct CF32 {
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
   }
+  template <int POL>
   __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*, uint32_t) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(g), r, vo, so, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(g), r, vo, so, POL);
   }
 };
 
@@ -130,6 +135,7 @@ struct CBF16 {
   }
   // Stochastic rounding to the 8-bit significand: add 16 random bits below
   // the kept ones to the magnitude, truncate.
+  template <int POL>
   __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables* t,
                             uint32_t rnd) {
     const uint32_t u = __float_as_uint(g * t->enc);
@@ -139,7 +145,7 @@ struct CBF16 {
     else if (mag < 0x7f7f0000u)
       mag = (mag + (rnd & 0xffffu)) & 0xffff0000u;
     __builtin_amdgcn_raw_buffer_store_b16(uint16_t(((u & 0x80000000u) | mag) >> 16), r, vo, so,
-                                          kStoreNT);
+                                          POL);
   }
 };
 
@@ -156,6 +162,7 @@ struct CFP16 {
   // [2^-14, 65504]: add 13 random bits below the kept ones to the float's
   // magnitude and truncate, which leaves a value FP16 holds exactly.  Below
   // the normal range (rare with the scale S) round to nearest even.
+  template <int POL>
   __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables* t,
                             uint32_t rnd) {
     const uint32_t u = __float_as_uint(g * t->enc);
@@ -163,7 +170,7 @@ struct CFP16 {
     if (mag >= 0x38800000u && mag < 0x477fe000u)
       mag = (mag + (rnd & 0x1fffu)) & 0xffffe000u;
     const _Float16 h = _Float16(__uint_as_float((u & 0x80000000u) | mag));
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, h), r, vo, so, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, h), r, vo, so, POL);
   }
 };
 
@@ -244,13 +251,14 @@ struct Macro {
 // Eq. (eq:summac) from the deviations: rho = 1 + sum g, rho u = sum g c
 // (sum w c = 0), and for the thermal set rho D T = D + sum g |c|^2 - rho u^2
 // (sum w |c|^2 = D); theta = T - 1.  Isothermal sets use T = 1.
-template <class L, class R>
-__device__ __forceinline__ Macro<R> macro(const R (&g)[L::Q]) {
+// A is the arithmetic type, G the type the deviations are held in.
+template <class L, class R, class G = R>
+__device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
   R drho = 0, mx = 0, my = 0, mz = 0, e2 = 0;
   auto body = [&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
-    const R v = g[q];
+    const R v = R(g[q]);
     drho += v;
     mx = add_scaled<ex>(mx, v);
     my = add_scaled<ey>(my, v);
@@ -275,14 +283,24 @@ __device__ __forceinline__ Macro<R> macro(const R (&g)[L::Q]) {
   return m;
 }
 
-// g* = g - omega (g - (f^eq - w)), in place.
-template <class L, class R>
-__device__ __forceinline__ void relax(R (&g)[L::Q], R omega) {
+// g* = g - omega (g - (f^eq - w)), in place.  With MOM, also writes the
+// output fields of the pre-collision state f~ at node n (Eq. (eq:summac)):
+// rho, u, T, and the stress and heat flux of the original f, obtained from
+// f~ by the conversion of Sec. II, f - f^eq = tau/(tau+1/2) (f~ - f^eq).
+// The stress / flux sums run over deviations only; their rest-state parts
+// are exact closed forms of the lattice's moments:
+//   sum_q w_q C_x C_y = u_x u_y,   sum_q w_q |C|^2 C_i = -u_i (D + 2 + |u|^2).
+template <class L, class R, bool MOM = false>
+__device__ __forceinline__ void relax(R (&g)[L::Q], R omega, double kfac = 0.0,
+                                      double* mom = nullptr, long long nodes = 0,
+                                      long long n = 0) {
   const Macro<R> m = macro<L, R>(g);
   const R uu = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
   const auto k = EqCoef<L, R>::make(m.rho, m.drho, uu, m.th);
   constexpr R r = R(L::R);
   const R sx = r * m.ux, sy = r * m.uy, sz = r * m.uz;
+  const R kf = R(kfac);
+  R sxy = 0, qx = 0, qy = 0, qz = 0;
   auto body = [&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
@@ -291,52 +309,30 @@ __device__ __forceinline__ void relax(R (&g)[L::Q], R omega) {
     x = add_scaled<ey>(x, sy);
     x = add_scaled<ez>(x, sz);
     const R geq = R(L::W[q]) * k.template poly<ex * ex + ey * ey + ez * ez>(x);
+    if constexpr (MOM) {
+      const R fp = geq + kf * (g[q] - geq);  // deviation of f from w
+      const R Cx = R(L::R * ex) - m.ux, Cy = R(L::R * ey) - m.uy, Cz = R(L::R * ez) - m.uz;
+      const R C2 = Cx * Cx + Cy * Cy + Cz * Cz;
+      sxy += fp * Cx * Cy;
+      qx += fp * C2 * Cx;
+      qy += fp * C2 * Cy;
+      qz += fp * C2 * Cz;
+    }
     g[q] = g[q] + omega * (geq - g[q]);
   };
   static_for<0, L::Q>(body);
-}
-
-// Output fields of one node from its deviations (always FP64): rho, u, T,
-// and the stress / heat flux of f = f^eq + kfac (f~ - f^eq) (conversion of
-// Sec. II).
-template <class L, class R>
-__device__ __forceinline__ void write_fields(const R (&gr)[L::Q], double kfac, double* mom,
-                                             long long nodes, long long n) {
-  double g[L::Q];
-  auto cvt = [&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    g[q] = double(gr[q]);
-  };
-  static_for<0, L::Q>(cvt);
-  const Macro<double> m = macro<L, double>(g);
-  const double uu = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
-  const auto k = EqCoef<L, double>::make(m.rho, m.drho, uu, m.th);
-  constexpr double r = L::R;
-  const double sx = r * m.ux, sy = r * m.uy, sz = r * m.uz;
-  double sxy = 0, qx = 0, qy = 0, qz = 0;
-  auto body = [&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
-    const double x = ex * sx + ey * sy + ez * sz;
-    const double geq = L::W[q] * k.template poly<ex * ex + ey * ey + ez * ez>(x);
-    const double fp = L::W[q] + geq + kfac * (g[q] - geq);
-    const double Cx = r * ex - m.ux, Cy = r * ey - m.uy, Cz = r * ez - m.uz;
-    const double C2 = Cx * Cx + Cy * Cy + Cz * Cz;
-    sxy += fp * Cx * Cy;
-    qx += fp * C2 * Cx;
-    qy += fp * C2 * Cy;
-    qz += fp * C2 * Cz;
-  };
-  static_for<0, L::Q>(body);
-  mom[0 * nodes + n] = m.rho;
-  mom[1 * nodes + n] = m.ux;
-  mom[2 * nodes + n] = m.uy;
-  mom[3 * nodes + n] = m.uz;
-  mom[4 * nodes + n] = 1.0 + m.th;
-  mom[5 * nodes + n] = sxy;
-  mom[6 * nodes + n] = 0.5 * qx;
-  mom[7 * nodes + n] = 0.5 * qy;
-  mom[8 * nodes + n] = 0.5 * qz;
+  if constexpr (MOM) {
+    const R rest = -(R(L::D + 2) + uu);
+    mom[0 * nodes + n] = 1.0 + double(m.drho);
+    mom[1 * nodes + n] = double(m.ux);
+    mom[2 * nodes + n] = double(m.uy);
+    mom[3 * nodes + n] = double(m.uz);
+    mom[4 * nodes + n] = 1.0 + double(m.th);
+    mom[5 * nodes + n] = double(m.ux * m.uy + sxy);
+    mom[6 * nodes + n] = 0.5 * double(m.ux * rest + qx);
+    mom[7 * nodes + n] = 0.5 * double(m.uy * rest + qy);
+    mom[8 * nodes + n] = 0.5 * double(m.uz * rest + qz);
+  }
 }
 
 // Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8,
@@ -467,11 +463,16 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
   const uint32_t nx = uint32_t(a.nx);
   const uint32_t pb = uint32_t(a.plane) * C::B;  // bytes per plane
   if (y >= L::N && y < a.ny - L::N) {
+    // vector offset: node (x - e_x, y - N), one per e_x; the row shift
+    // (N - e_y) rows joins the plane offset in the scalar operand
+    uint32_t vo[2 * NS + 1];
+    const uint32_t yb = uint32_t(y - L::N) * nx;
+    for (int s = 0; s < 2 * NS + 1; ++s) vo[s] = (yb + uint32_t(xw[s])) * C::B;
+    const uint32_t rb = nx * C::B;  // bytes per row
     auto body = [&](auto qc) {
       constexpr int q = decltype(qc)::value;
       constexpr int ex = L::E[q][0], ey = L::E[q][1];
-      f[q] = C::ld(fin, (uint32_t(y - ey) * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(q) * pb,
-                   a.tab);
+      f[q] = C::ld(fin, vo[ex + NS], uint32_t(q) * pb + uint32_t(L::N - ey) * rb, a.tab);
     };
     static_for<0, L::Q>(body);
   } else {
@@ -493,17 +494,18 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
   }
 }
 
-template <class L, class C>
+template <class L, class C, int POL = kStoreNT>
 __device__ __forceinline__ void store(const typename C::R (&f)[L::Q], const StepArgs& a,
                                       uint32_t n) {
   const Rsrc fout = plane_set<L, C>(a.fout, a.plane);
   const uint32_t pb = uint32_t(a.plane) * C::B;
   // counter for the stochastic rounding of 16-bit formats: (node, q, step)
-  const uint32_t key = C::kRandom ? mix32(a.step * 0x9e3779b9u + a.seed) ^ (n * uint32_t(L::Q)) : 0u;
+  const uint32_t key =
+      C::kRandom ? mix32(a.step * 0x9e3779b9u + a.seed) ^ (n * uint32_t(L::Q)) : 0u;
   auto body = [&](auto qc) {
     constexpr int q = decltype(qc)::value;
     const uint32_t rnd = C::kRandom ? mix32(key + uint32_t(q) * 0x85ebca77u) : 0u;
-    C::st(fout, n * C::B, uint32_t(q) * pb, f[q], a.tab, rnd);
+    C::template st<POL>(fout, n * C::B, uint32_t(q) * pb, f[q], a.tab, rnd);
   };
   static_for<0, L::Q>(body);
 }
@@ -545,8 +547,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
   R f[L::Q];
   pull<L, C>(f, a, y, xw,
              [&](int wall, int ex) { return a.ratio[wall * a.nx + xw[ex + NS]]; });
-  if constexpr (MOM) write_fields<L, R>(f, a.kfac, a.mom, nodes, n);
-  relax<L, R>(f, R(a.omega));
+  relax<L, R, MOM>(f, R(a.omega), a.kfac, a.mom, nodes, n);
   store<L, C>(f, a, uint32_t(n));
 }
 
@@ -584,8 +585,7 @@ __global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
              [&](int, int ex) { return ratio_s[int(threadIdx.x) - ex + NS]; });
   const long long nodes = (long long)a.nx * a.ny;
   const uint32_t n = uint32_t(y) * uint32_t(a.nx) + uint32_t(x);
-  if constexpr (MOM) write_fields<L, R>(f, a.kfac, a.mom, nodes, n);
-  relax<L, R>(f, R(a.omega));
+  relax<L, R, MOM>(f, R(a.omega), a.kfac, a.mom, nodes, n);
   store<L, C>(f, a, n);
 }
 
@@ -616,9 +616,141 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double* 
     f[q] = R(L::W[q] * k.template poly<ex * ex + ey * ey + ez * ez>(x));  // f^eq - w
   };
   static_for<0, L::Q>(body);
-  write_fields<L, R>(f, a.kfac, a.mom, nodes, n);
-  relax<L, R>(f, R(a.omega));
+  relax<L, R, true>(f, R(a.omega), a.kfac, a.mom, nodes, n);
   store<L, C>(f, a, uint32_t(n));
+}
+
+// Fixed-order block reduction of four FP64 partial sums over NT threads;
+// every thread gets the totals.
+template <int NT = kBlock>
+__device__ __forceinline__ void block_sum4(double (&v)[4], double (*sh)[NT]) {
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  for (int k = 0; k < 4; ++k) v[k] = sh[k][0];
+  __syncthreads();  // the scratch may be reused right away
+}
+
+// Mass, residual sums and nonfinite count of one node's fields; the
+// residual snapshot is advanced to the current fields.
+__device__ __forceinline__ void residual_terms(const double* mom, double* snap, long long n,
+                                               long long i, double (&v)[4]) {
+  const double rho = mom[i];
+  const double ux = mom[n + i], uy = mom[2 * n + i], uz = mom[3 * n + i];
+  const double T = mom[4 * n + i];
+  const double dx = ux - snap[i], dy = uy - snap[n + i], dz = uz - snap[2 * n + i];
+  const double dT = T - snap[3 * n + i];
+  snap[i] = ux;
+  snap[n + i] = uy;
+  snap[2 * n + i] = uz;
+  snap[3 * n + i] = T;
+  v[0] += rho;
+  v[1] += dx * dx + dy * dy + dz * dz;
+  v[2] += dT * dT;
+  v[3] += isfinite(rho + ux + uy + uz + T) ? 0.0 : 1.0;
+}
+
+// ---------------------------------------------------------- batched cases --
+// Persistent update of many small channels: workgroup b owns case b and runs
+// its steps itself, so a step costs two workgroup barriers instead of two
+// kernel launches.  Per step: each wavefront reduces the pooled mass of
+// (wall, ghost column) pairs with a lane-shuffle butterfly into LDS,
+// barrier, the threads update the case's nodes (pulls from the ping-pong
+// buffers, which stay in cache), barrier.  Steps run in residual windows;
+// after each window the case's fields, mass and residual are formed in the
+// kernel and the case stops once the residual is below its tolerance.  A
+// case's arithmetic and stopping point depend only on its own data, so its
+// result is the same alone and in any mix, and whatever its step budget.
+template <class L, class C>
+__device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, double* ratio_s,
+                                         double (*red)[kBatchBlock]) {
+  using R = typename C::R;
+  constexpr int NS = max_ex<L>();
+  StepArgs a = cd.a;
+  const int nodes = a.nx * a.ny;
+  const int lane = int(threadIdx.x & 63);
+  const int wave = int(threadIdx.x >> 6);
+  constexpr int kWaves = kBatchBlock / 64;
+  const int W = cd.window;
+  int cur = cd.cur;
+  int done = 0;
+  double res = __builtin_inf(), mass = 0.0, state = 0.0;
+  while (done + W <= cd.budget) {
+    for (int s = 0; s < W; ++s) {
+      a.fin = cd.f[cur];
+      a.fout = cd.f[cur ^ 1];
+      a.step = cd.a.step + uint32_t(done + s) + 1u;
+      const Rsrc fin = plane_set<L, C>(a.fin, a.plane);
+      for (int p = wave; p < 2 * a.nx; p += kWaves) {
+        const bool top = p >= a.nx;
+        const int xp = top ? p - a.nx : p;
+        const double M = top ? ghost_mass<L, C, true>(fin, a, xp, lane)
+                             : ghost_mass<L, C, false>(fin, a, xp, lane);
+        if (lane == 0)
+          ratio_s[p] = top ? (a.tab->Wt + M) / a.tab->Dt : (a.tab->Wb + M) / a.tab->Db;
+      }
+      __syncthreads();
+      const bool last = s == W - 1;
+      for (int n = threadIdx.x; n < nodes; n += kBatchBlock) {
+        const int y = n / a.nx;
+        const int x = n - y * a.nx;
+        int xw[2 * NS + 1];
+        wrapped_columns<NS, false>(x, a.nx, xw);
+        R f[L::Q];
+        pull<L, C>(f, a, y, xw,
+                   [&](int wall, int ex) { return ratio_s[wall * a.nx + xw[ex + NS]]; });
+        if (last)
+          relax<L, R, true>(f, R(a.omega), a.kfac, a.mom, nodes, n);
+        else
+          relax<L, R>(f, R(a.omega));
+        store<L, C, kStoreCached>(f, a, uint32_t(n));
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    done += W;
+    double v[4] = {0, 0, 0, 0};
+    for (int i = threadIdx.x; i < nodes; i += kBatchBlock) residual_terms(a.mom, cd.snap, nodes, i, v);
+    block_sum4<kBatchBlock>(v, red);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 4; ++k) cd.result[k] = v[k];
+    const double ru = sqrt(v[1]) / (double(W) * cd.uref * sqrt(double(nodes)));
+    const double rt = sqrt(v[2]) / (double(W) * sqrt(double(nodes)));
+    mass = v[0];
+    if (v[3] != 0.0) {  // the same decision in every thread: v came from LDS
+      res = __builtin_nan("");
+      state = -1.0;
+      break;
+    }
+    res = fmax(ru, rt);
+    if (res < cd.tol) {
+      state = 1.0;
+      break;
+    }
+  }
+  if (threadIdx.x == 0) {
+    out[blockIdx.x].residual = res;
+    out[blockIdx.x].mass = mass;
+    out[blockIdx.x].steps = double(done);
+    out[blockIdx.x].state = state;
+  }
+}
+
+template <class C>
+__global__ __launch_bounds__(kBatchBlock) void batch_kernel(const CaseDesc* __restrict__ cases,
+                                                            CaseOut* out) {
+  __shared__ double ratio_s[2 * kBatchMaxNx];
+  __shared__ double red[4][kBatchBlock];
+  const CaseDesc& cd = cases[blockIdx.x];
+  switch (cd.lattice) {
+    case 0: run_case<D2Q16, C>(cd, out, ratio_s, red); break;
+    case 1: run_case<D2Q17, C>(cd, out, ratio_s, red); break;
+    case 2: run_case<D3Q121, C>(cd, out, ratio_s, red); break;
+  }
 }
 
 // hipGetLastError reports the last error of any HIP call on this thread,
@@ -679,6 +811,25 @@ hipError_t SetOps<L, C>::init(const StepArgs& a, const double* fields, hipStream
   return hipGetLastError();
 }
 #endif
+
+// Batched persistent launch of one storage format (lbm_batch_*.hip).
+template <class C>
+hipError_t batch_launch(const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s);
+
+#ifdef LBM_DEFINE_BATCH
+template <class C>
+hipError_t batch_launch(const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s) {
+  clear_stale_error();
+  hipLaunchKernelGGL((batch_kernel<C>), dim3(unsigned(ncase)), dim3(kBatchBlock), 0, s, cases,
+                     out);
+  return hipGetLastError();
+}
+#endif
+
+extern template hipError_t batch_launch<CF64>(const CaseDesc*, int, CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF32>(const CaseDesc*, int, CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CBF16>(const CaseDesc*, int, CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CFP16>(const CaseDesc*, int, CaseOut*, hipStream_t);
 
 extern template struct SetOps<D2Q16, CF64>;
 extern template struct SetOps<D2Q16, CF32>;

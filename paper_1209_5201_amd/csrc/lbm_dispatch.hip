@@ -8,37 +8,13 @@ namespace dev {
 // ----------------------------------------------------------- reductions --
 // Fixed grid and fixed combination order: the FP64 results are
 // deterministic for a given problem size.
-__device__ __forceinline__ void block_sum4(double (&v)[4], double (*sh)[kBlock]) {
-  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = v[k];
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s)
-      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
-    __syncthreads();
-  }
-  for (int k = 0; k < 4; ++k) v[k] = sh[k][0];
-}
-
 __global__ __launch_bounds__(kBlock) void reduce_partial(ReduceArgs r) {
   __shared__ double sh[4][kBlock];
   const long long n = r.nodes;
   double v[4] = {0, 0, 0, 0};
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kBlock) {
-    const double rho = r.mom[i];
-    const double ux = r.mom[n + i], uy = r.mom[2 * n + i], uz = r.mom[3 * n + i];
-    const double T = r.mom[4 * n + i];
-    const double dx = ux - r.snap[i], dy = uy - r.snap[n + i], dz = uz - r.snap[2 * n + i];
-    const double dT = T - r.snap[3 * n + i];
-    r.snap[i] = ux;
-    r.snap[n + i] = uy;
-    r.snap[2 * n + i] = uz;
-    r.snap[3 * n + i] = T;
-    v[0] += rho;
-    v[1] += dx * dx + dy * dy + dz * dz;
-    v[2] += dT * dT;
-    v[3] += isfinite(rho + ux + uy + uz + T) ? 0.0 : 1.0;
-  }
+       i += (long long)gridDim.x * kBlock)
+    residual_terms(r.mom, r.snap, n, i, v);
   block_sum4(v, sh);
   if (threadIdx.x == 0)
     for (int k = 0; k < 4; ++k) r.partial[blockIdx.x * 4 + k] = v[k];
@@ -117,6 +93,17 @@ hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(dev::reduce_final, dim3(1), dim3(kBlock), 0, s, r);
   return hipGetLastError();
+}
+
+hipError_t launch_batch(int prec, const CaseDesc* cases, int ncase, CaseOut* out,
+                        hipStream_t s) {
+  switch (prec) {
+    case kFP64: return dev::batch_launch<dev::CF64>(cases, ncase, out, s);
+    case kFP32: return dev::batch_launch<dev::CF32>(cases, ncase, out, s);
+    case kBF16: return dev::batch_launch<dev::CBF16>(cases, ncase, out, s);
+    case kFP16: return dev::batch_launch<dev::CFP16>(cases, ncase, out, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 // Host copy of the equilibrium used for the wall Maxwellians (same

@@ -52,7 +52,31 @@ struct ReduceArgs {
   long long nodes;
 };
 
-// Launchers (lbm_kernels.hip).  lattice: 0 D2Q16, 1 D2Q17, 2 D3Q121.
+// One channel of a batched launch (lbm_batch_step): the step arguments of a
+// context plus its buffers.  Built on the host, copied to the device.
+constexpr int kBatchMaxNx = 64;    // ghost-column ratios of a case live in LDS
+constexpr int kBatchBlock = 256;   // threads per case of the batched kernel
+struct CaseDesc {
+  StepArgs a;           // fin/fout/step are set per step from f, cur, steps
+  void* f[2];
+  double* snap;         // residual snapshot of the context
+  double* result;       // mass, sum du^2, sum dT^2, nonfinite count
+  double uref;          // velocity scale of the residual
+  double tol;           // stop after a window whose residual is below tol
+  int cur;              // f[cur] holds the newest f*
+  int lattice;
+  int window;           // steps per residual window
+  int budget;           // most steps this launch (a multiple of window)
+};
+// Per-case output of a batched launch.
+struct CaseOut {
+  double residual;      // residual of the last window (NaN: non-finite)
+  double mass;
+  double steps;         // steps advanced
+  double state;         // 1 converged, 0 budget used up, -1 non-finite
+};
+
+// Launchers (lbm_set_*.hip, lbm_dispatch.hip).  lattice: 0 D2Q16, 1 D2Q17, 2 D3Q121.
 hipError_t launch_wall(int lattice, int prec, const StepArgs& a, hipStream_t s);
 hipError_t launch_step(int lattice, int prec, const StepArgs& a, bool moments,
                        hipStream_t s);
@@ -65,6 +89,12 @@ hipError_t launch_step_rows(int lattice, int prec, const StepArgs& a, bool momen
 hipError_t launch_init(int lattice, int prec, const StepArgs& a,
                        const double* fields, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s);
+// One workgroup per case advances every case of one storage precision in
+// windows of cases[i].window steps, up to cases[i].budget steps, stopping a
+// case after the first window whose residual is below cases[i].tol; writes
+// each case's fields after its last window, its mass / residual sums into
+// its result block, and out[i].
+hipError_t launch_batch(int prec, const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s);
 
 // Host helpers (no device work).
 // g^eq_q(u, T) of every velocity with unit density (wall Maxwellians).

@@ -93,6 +93,12 @@ def _load():
         "lbm_state_bytes": (ctypes.c_size_t, [_vp]),
         "lbm_save": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
         "lbm_load": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+        "lbm_batch_step": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64,
+                                          _dp]),
+        "lbm_batch_run": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                         ctypes.c_double, _dp, ctypes.POINTER(ctypes.c_int64),
+                                         _ip]),
         "lbm_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
         "lbm_kernel_time": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp,
                                            ctypes.POINTER(ctypes.c_int64)]),
@@ -113,7 +119,7 @@ def exported_symbols():
     return ["lbm_lattice_info", "lbm_tau_from_kn", "lbm_required_bytes", "lbm_create",
             "lbm_create_in", "lbm_init", "lbm_step", "lbm_field", "lbm_moments",
             "lbm_residual", "lbm_mass", "lbm_steps_done", "lbm_state_bytes", "lbm_save",
-            "lbm_load", "lbm_set_timing", "lbm_kernel_time", "lbm_destroy", "lbm_strerror",
+            "lbm_load", "lbm_batch_step", "lbm_batch_run", "lbm_set_timing", "lbm_kernel_time", "lbm_destroy", "lbm_strerror",
             "lbm_last_device_error"]
 
 
@@ -235,6 +241,32 @@ def lbm_save(ctx) -> bytearray:
 def lbm_load(ctx, state: bytearray):
     cbuf = (ctypes.c_char * len(state)).from_buffer(state)
     _check(_load().lbm_load(ctx, ctypes.cast(cbuf, _vp), len(state)), "lbm_load")
+
+
+def lbm_batch_step(ctxs, k_steps: int) -> np.ndarray:
+    """Advance several contexts k_steps in one persistent launch per storage
+    format; returns their residuals (NaN where a case went non-finite)."""
+    n = len(ctxs)
+    arr = (_vp * n)(*[c.value if isinstance(c, _vp) else c for c in ctxs])
+    out = np.empty(n, dtype=np.float64)
+    _check(_load().lbm_batch_step(arr, n, int(k_steps), _dptr(out)), "lbm_batch_step")
+    return out
+
+
+def lbm_batch_run(ctxs, budgets, window: int, tol: float):
+    """Advance contexts in residual windows until converged (residual < tol)
+    or out of budget; returns (residuals, steps advanced, states)."""
+    n = len(ctxs)
+    arr = (_vp * n)(*[c.value if isinstance(c, _vp) else c for c in ctxs])
+    b = np.ascontiguousarray(budgets, dtype=np.int64)
+    res = np.empty(n, dtype=np.float64)
+    steps = np.empty(n, dtype=np.int64)
+    state = np.empty(n, dtype=np.int32)
+    _check(_load().lbm_batch_run(arr, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 int(window), float(tol), _dptr(res),
+                                 steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 state.ctypes.data_as(_ip)), "lbm_batch_run")
+    return res, steps, state
 
 
 def lbm_set_timing(ctx, enable: bool):
