@@ -154,6 +154,34 @@ def serving(n_requests: int, rate: float, baseline_cases: int):
                          "batched_fp32_same_requests_solves_per_s": r(same["solves_per_s"])}}
 
 
+def precision_table(torch, steps_2d: int = 200, steps_3d: int = 60):
+    """MLUPS and algorithmic HBM rate of the fused update per velocity set and
+    storage format: the bulk D2Q17 2048^2 case and the D3Q121 1024^2 case
+    (walls -0.1 / +0.1, Kn 0.05).  Wall clock over back-to-back steps (one
+    launch per step); fields refreshed once at the end."""
+    import paper_1209_5201_amd as lbm
+    from paper_1209_5201_amd import workloads as W
+    rows = []
+    for lat, nx, ny, steps, walls in (
+            ("D2Q17", 2048, 2048, steps_2d, (W.C3["bottom"], W.C3["top"])),
+            ("D3Q121", W.C5["nx"], W.C5["ny"], steps_3d, (W.C5["bottom"], W.C5["top"]))):
+        Q = lbm.lbm_lattice_info(lat)["Q"]
+        for prec, b in (("fp64", 8), ("fp32", 4), ("bf16", 2), ("fp16", 2)):
+            ch = lbm.Channel(lat, nx, ny, lbm.lbm_tau_from_kn(lat, ny, 0.05), *walls, prec=prec)
+            ch.step(10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ch.step(steps)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            ch.close()
+            gbps = 2.0 * Q * b * nx * ny / dt / 1e9
+            rows.append({"lattice": lat, "grid": "%dx%d" % (nx, ny), "precision": prec,
+                         "MLUPS": round(nx * ny / dt / 1e6, 1), "us_per_step": round(dt * 1e6, 1),
+                         "alg_GBps": round(gbps, 1), "frac_hbm": round(gbps / HBM_PEAK_GBPS, 3)})
+    return rows
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
     """Device-to-device copy rate (read + write bytes / time) as a practical
     HBM ceiling, measured in the same run."""
@@ -182,6 +210,7 @@ def main():
     ap.add_argument("--serving-rate", type=float, default=100.0)
     ap.add_argument("--serving-baseline", type=int, default=16)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-precisions", action="store_true")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(args.traffic_from[0], args.traffic_from[1],
@@ -261,6 +290,8 @@ def main():
         "mass_after": mass,
     }
     ch.close()
+    if not args.no_precisions:
+        line["precisions"] = precision_table(torch)
     if not args.no_serving:
         line["serving"] = serving(args.serving_requests, args.serving_rate,
                                   args.serving_baseline)

@@ -132,3 +132,52 @@ def test_served_fp32_results_match_fp64_oracle():
             w = want[k][:, 0]
             scale = np.abs(w - (1.0 if k == "T" else 0.0)).max()
             assert np.abs(res.profiles[k] - w).max() <= 1e-5 * scale + 1e-9, (req["lattice"], k)
+
+
+def poison(ch):
+    """Overwrite node 0's first population with NaN through a checkpoint:
+    the failure is forced from the host; the GPU only computes with it."""
+    state = ch.save()
+    nan = np.array([np.nan], dtype=np.float32 if ch.prec == "fp32" else np.float64)
+    state[16:16 + nan.nbytes] = nan.tobytes()
+    ch.load(state)
+
+
+def test_nonfinite_state_is_reported_not_crashed():
+    say("case nonfinite")
+    ch = open_case("D2Q17", 1, 32, 0.1, (-0.1, 0, 1.0), (0.1, 0, 1.0), "fp32")
+    ch.step(20)
+    poison(ch)
+    ch.step(20)
+    with pytest.raises(lbm.LbmError) as ei:
+        ch.residual()
+    assert ei.value.status == lbm.lbm.LBM_ENONFINITE
+    ch.close()
+
+
+def test_poisoned_case_retires_without_touching_the_others():
+    say("case poisoned batch")
+    good = [open_case(*c, "fp32") for c in CASES[:3]]
+    ref = [open_case(*c, "fp32") for c in CASES[:3]]
+    bad = open_case(*CASES[1], "fp32")
+    poison(bad)
+    r1, s1, st1 = lbm.lbm_batch_run([c.ctx for c in good] + [bad.ctx], [4000] * 4, 100, 1e-7)
+    r2, s2, st2 = lbm.lbm_batch_run([c.ctx for c in ref], [4000] * 3, 100, 1e-7)
+    assert st1[3] == -1 and np.isnan(r1[3]) and s1[3] == 100
+    assert np.array_equal(s1[:3], s2) and np.array_equal(st1[:3], st2)
+    for a, b in zip(good, ref):
+        for k in ("ux", "T", "sxy"):
+            assert np.array_equal(a.field(k), b.field(k))
+    for c in good + ref + [bad]:
+        c.close()
+
+
+def test_grid_convergence_is_second_order():
+    """Sec. IV: thermal Couette (D3Q121, Kn = 0.01, U_w = 0.2, T_w = 1); the
+    global errors E_U, E_T against a fine reference fall at second order."""
+    from paper_1209_5201_amd import convergence
+    say("case grid convergence")
+    out = convergence.convergence_study(grids=(20, 40, 80), reference=320)
+    say("   ", out)
+    assert 1.7 < out["order_U"] < 2.5, out
+    assert 1.7 < out["order_T"] < 2.5, out
