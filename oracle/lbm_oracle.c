@@ -26,9 +26,16 @@
  *   2. post-collision f* = f~ - (f~ - f^eq)/(tau + 1/2)   (dt = 1);
  *   3. stream every f* along its integer velocity; what leaves the fluid
  *      lands in an explicit ghost array as the incoming f^I (Sec. III);
- *   4. per ghost column, pool all incoming mass over all layers and re-emit
- *      it along every outgoing velocity of every layer in proportion to the
- *      wall Maxwellian, Eq. (eq:dkboundary);
+ *   4. the wall turns incoming into outgoing populations through the
+ *      scattering kernel R of Sec. III, taken of Maxwell's form
+ *      R = alpha R_D + (1 - alpha) R_S per wall:
+ *        - diffuse part R_D (the paper's wall, alpha = 1): per ghost column,
+ *          pool all incoming mass over all layers and re-emit the fraction
+ *          alpha of it along every outgoing velocity of every layer in
+ *          proportion to the wall Maxwellian, Eq. (eq:dkboundary);
+ *        - specular part R_S: the fraction 1 - alpha of each incoming
+ *          population is sent back with its normal velocity reversed, from
+ *          the ghost cell where a mirror at the wall plane would put it;
  *   5. the outgoing f^O stream into the fluid in the same step.
  */
 #include <math.h>
@@ -120,8 +127,10 @@ static int wrap(int x, int nx)
  * columns: incoming and outgoing mass of the bottom wall, then of the top. */
 static void one_step(const olat *L, int nx, int ny, double omega,
                      const double *gb, const double *gt,
+                     double alpha_b, double alpha_t, const int *mirror,
                      double *f, double *fs, double *fn,
-                     double *ghb, double *ght, double *flux)
+                     double *ghb, double *ght, double *gob, double *got,
+                     double *flux)
 {
     const int Q = L->Q, N = max_ey(L);
     const size_t nodes = (size_t)nx * (size_t)ny;
@@ -168,7 +177,16 @@ static void one_step(const olat *L, int nx, int ny, double omega,
                 Dt += gt[a];
         }
 
-    /* 4-5. per ghost column: pool the incoming mass, emit f^O, stream it */
+    /* 4. outgoing ghost populations f^O from the generic scattering closure
+     * of Sec. III, f^O = sum over incoming of R f^I, with
+     *   R = alpha R_D + (1 - alpha) R_S:
+     * R_D (Eq. (eq:dkboundary)) pools all incoming mass of a ghost column and
+     * re-emits it in proportion to the wall Maxwellian; R_S (specular) sends
+     * each incoming particle back with its normal velocity reversed, from the
+     * mirror-image ghost position, so that it continues its straight path
+     * reflected at the wall (half a spacing outside the first fluid row). */
+    memset(gob, 0, (size_t)N * nx * Q * sizeof(double));
+    memset(got, 0, (size_t)N * nx * Q * sizeof(double));
     for (x = 0; x < nx; ++x) {
         double Mb = 0.0, Mt = 0.0;
         for (l = 0; l < N; ++l)
@@ -182,22 +200,50 @@ static void one_step(const olat *L, int nx, int ny, double omega,
         in_t += Mt;
         for (l = 0; l < N; ++l)
             for (a = 0; a < Q; ++a) {
+                if (L->e[3 * a + 1] > l)
+                    gob[((size_t)l * nx + x) * Q + a] += alpha_b * Mb / Db * gb[a];
+                if (-L->e[3 * a + 1] > l)
+                    got[((size_t)l * nx + x) * Q + a] += alpha_t * Mt / Dt * gt[a];
+            }
+    }
+    for (x = 0; x < nx; ++x)
+        for (l = 0; l < N; ++l)
+            for (a = 0; a < Q; ++a) {
+                /* a particle of velocity (ex, ey, ez) that landed in ghost
+                 * (x, layer l) came from fluid row -ey - l - 1; reflected, it
+                 * leaves ghost (x - ex, that layer) with velocity (ex, -ey, ez) */
+                int ey = L->e[3 * a + 1];
+                if (ey < -l) {
+                    int lm = -ey - l - 1, xm = wrap(x - L->e[3 * a], nx);
+                    gob[((size_t)lm * nx + xm) * Q + mirror[a]] +=
+                        (1.0 - alpha_b) * ghb[((size_t)l * nx + x) * Q + a];
+                }
+                if (-ey < -l) {
+                    int lm = ey - l - 1, xm = wrap(x - L->e[3 * a], nx);
+                    got[((size_t)lm * nx + xm) * Q + mirror[a]] +=
+                        (1.0 - alpha_t) * ght[((size_t)l * nx + x) * Q + a];
+                }
+            }
+
+    /* 5. the outgoing populations stream into the fluid in the same step */
+    for (x = 0; x < nx; ++x)
+        for (l = 0; l < N; ++l)
+            for (a = 0; a < Q; ++a) {
                 if (L->e[3 * a + 1] > l) {
-                    double fo = Mb / Db * gb[a];
+                    double fo = gob[((size_t)l * nx + x) * Q + a];
                     int xd = wrap(x + L->e[3 * a], nx);
                     int yd = -(l + 1) + L->e[3 * a + 1];
                     fn[((size_t)yd * nx + xd) * Q + a] = fo;
                     out_b += fo;
                 }
                 if (-L->e[3 * a + 1] > l) {
-                    double fo = Mt / Dt * gt[a];
+                    double fo = got[((size_t)l * nx + x) * Q + a];
                     int xd = wrap(x + L->e[3 * a], nx);
                     int yd = ny + l + L->e[3 * a + 1];
                     fn[((size_t)yd * nx + xd) * Q + a] = fo;
                     out_t += fo;
                 }
             }
-    }
     memcpy(f, fn, nodes * Q * sizeof(double));
     if (flux) {
         flux[0] = in_b;
@@ -238,13 +284,15 @@ void orc_init(int Q, int D, int eq_order, int thermal, const int *e,
 }
 
 /* Advance f~ by nsteps.  wall_b/wall_t = {ux, uz, T} of each wall
- * (tangential velocities only).  tau is the relaxation time in time steps;
- * +inf gives the collisionless limit.  flux (may be NULL): 4 doubles per
- * step, see one_step().  Returns 0, or -1 on allocation failure. */
+ * (tangential velocities only); alpha_b/alpha_t their accommodation (1:
+ * diffuse, Eq. (eq:dkboundary); 0: specular).  tau is the relaxation time in
+ * time steps; +inf gives the collisionless limit.  flux (may be NULL): 4
+ * doubles per step, see one_step().  Returns 0, -1 on allocation failure,
+ * -2 if a velocity has no mirror image in the set. */
 int orc_run(int Q, int D, int eq_order, int thermal, const int *e,
             const double *w, double r, int nx, int ny, double tau,
-            const double *wall_b, const double *wall_t, double *f,
-            long nsteps, double *flux)
+            const double *wall_b, const double *wall_t, double alpha_b,
+            double alpha_t, double *f, long nsteps, double *flux)
 {
     olat L = {Q, D, eq_order, thermal, e, w, r};
     const int N = max_ey(&L);
@@ -258,9 +306,12 @@ int orc_run(int Q, int D, int eq_order, int thermal, const int *e,
     double *fn = malloc(nodes * Q * sizeof(double));
     double *ghb = malloc((size_t)N * nx * Q * sizeof(double));
     double *ght = malloc((size_t)N * nx * Q * sizeof(double));
+    double *gob = malloc((size_t)N * nx * Q * sizeof(double));
+    double *got = malloc((size_t)N * nx * Q * sizeof(double));
+    int *mirror = malloc(Q * sizeof(int));
     long s;
-    int a, rc = 0;
-    if (!gb || !gt || !fs || !fn || !ghb || !ght) {
+    int a, b, rc = 0;
+    if (!gb || !gt || !fs || !fn || !ghb || !ght || !gob || !got || !mirror) {
         rc = -1;
         goto done;
     }
@@ -269,9 +320,21 @@ int orc_run(int Q, int D, int eq_order, int thermal, const int *e,
         gb[a] = geq(&L, a, ub, thermal ? wall_b[2] : 1.0);
         gt[a] = geq(&L, a, ut, thermal ? wall_t[2] : 1.0);
     }
+    /* mirror[a]: the velocity with the normal component reversed */
+    for (a = 0; a < Q; ++a) {
+        mirror[a] = -1;
+        for (b = 0; b < Q; ++b)
+            if (e[3 * b] == e[3 * a] && e[3 * b + 1] == -e[3 * a + 1] &&
+                e[3 * b + 2] == e[3 * a + 2])
+                mirror[a] = b;
+        if (mirror[a] < 0) {
+            rc = -2;
+            goto done;
+        }
+    }
     for (s = 0; s < nsteps; ++s)
-        one_step(&L, nx, ny, omega, gb, gt, f, fs, fn, ghb, ght,
-                 flux ? flux + 4 * s : NULL);
+        one_step(&L, nx, ny, omega, gb, gt, alpha_b, alpha_t, mirror, f, fs, fn,
+                 ghb, ght, gob, got, flux ? flux + 4 * s : NULL);
 done:
     free(gb);
     free(gt);
@@ -279,6 +342,9 @@ done:
     free(fn);
     free(ghb);
     free(ght);
+    free(gob);
+    free(got);
+    free(mirror);
     return rc;
 }
 

@@ -54,8 +54,8 @@ def _load():
                                            _dp, _dp]
             lib.orc_init.restype = None
             lib.orc_run.argtypes = lat + [ctypes.c_int, ctypes.c_int,
-                                          ctypes.c_double, _dp, _dp, _dp,
-                                          ctypes.c_long, _dp]
+                                          ctypes.c_double, _dp, _dp, ctypes.c_double,
+                                          ctypes.c_double, _dp, ctypes.c_long, _dp]
             lib.orc_run.restype = ctypes.c_int
             lib.orc_moments.argtypes = lat + [ctypes.c_int, ctypes.c_int,
                                               ctypes.c_double, _dp, _dp]
@@ -111,11 +111,15 @@ class OracleCase:
     """One channel: nx periodic columns, ny rows between two diffuse walls.
 
     walls are (ux, uz, T) per wall; bottom wall below row 0, top above row
-    ny-1.  Initial fields default to rho = 1, u = 0, T = 1.
+    ny-1; accommodation = (alpha_b, alpha_t) of the Maxwell-type scattering
+    kernel (1: fully diffuse, the paper's wall).  Initial fields default to
+    rho = 1, u = 0, T = 1.
     """
 
     def __init__(self, lattice, nx, ny, tau, wall_b=(0.0, 0.0, 1.0),
-                 wall_t=(0.0, 0.0, 1.0), rho0=None, u0=None, T0=None):
+                 wall_t=(0.0, 0.0, 1.0), rho0=None, u0=None, T0=None,
+                 accommodation=(1.0, 1.0)):
+        self.alpha = (float(accommodation[0]), float(accommodation[1]))
         self.lat = _lat.by_name(lattice) if isinstance(lattice, str) else lattice
         self._la = _LatArgs(self.lat)
         self.nx, self.ny, self.tau = int(nx), int(ny), float(tau)
@@ -140,10 +144,10 @@ class OracleCase:
     def run(self, nsteps: int, record_flux: bool = False):
         flux = np.zeros((max(int(nsteps), 1), 4)) if record_flux else None
         rc = _load().orc_run(*self._la.args(), self.nx, self.ny, self.tau,
-                             _p(self.wall_b), _p(self.wall_t), _p(self.f),
-                             int(nsteps), _p(flux) if record_flux else None)
+                             _p(self.wall_b), _p(self.wall_t), self.alpha[0], self.alpha[1],
+                             _p(self.f), int(nsteps), _p(flux) if record_flux else None)
         if rc != 0:
-            raise MemoryError("oracle allocation failed")
+            raise RuntimeError("oracle run failed (%d)" % rc)
         self.t += int(nsteps)
         return flux[:nsteps] if record_flux else None
 
