@@ -182,6 +182,17 @@ int lbm_batch_step(lbm_ctx *const *ctxs, int n_ctx, int64_t k_steps, double *res
 int lbm_batch_run(lbm_ctx *const *ctxs, int n_ctx, const int64_t *budgets, int64_t window,
                   double tol, double *residuals_out, int64_t *steps_out, int *state_out);
 
+/* Accommodation of each wall: the wall scatters with Maxwell's kernel
+ * R = alpha R_D + (1 - alpha) R_S, built on the generic scattering kernel
+ * of Sec. III: the fraction alpha of the incoming mass is re-emitted
+ * diffusely (R_D, Eq. (eq:dkboundary)), the rest is reflected specularly
+ * (normal velocity reversed, from the mirror-image ghost cell).  alpha = 1
+ * (the default after lbm_create) is the paper's wall, alpha = 0 a specular
+ * wall.  Applies to every later step of the context.  Requires
+ * 0 <= alpha <= 1 for both walls, else LBM_EINVAL and nothing changes.
+ * Synchronizes the context stream. */
+int lbm_set_accommodation(lbm_ctx *ctx, double alpha_bottom, double alpha_top);
+
 /* Kernel timing with HIP events (profiling aid).  While enabled, lbm_step
  * brackets every launch of the wall-sum kernel and of the fused update kernel
  * with events on the context stream and accumulates their durations; the

@@ -20,6 +20,7 @@ struct lbm_ctx {
   int nx, ny, Q, N, D;
   double tau, r;
   lbm_wall wb, wt;
+  double alpha_b, alpha_t;  // accommodation (1: the paper's diffuse wall)
   hipStream_t stream;
   bool owns;
   char* base;
@@ -170,6 +171,8 @@ bool fill_tables(lbm_ctx* c, Tables* t) {
   // 16-bit codecs: FP16 keeps (f - w) * 2^12 (deviations |f - w| < 1 fit its
   // range, small ones stay normal); BF16 has FP32's range, scale 1.
   // Wb/Wt enter the pooled mass as M = W + sum of deviations.
+  t->ab = c->alpha_b;
+  t->at = c->alpha_t;
   const float S = c->prec == kFP16 ? 4096.0f : 1.0f;
   t->dec = 1.0f / S;
   t->enc = S;
@@ -220,6 +223,7 @@ int create_common(lbm_lattice lattice, lbm_grid grid, double tau, const lbm_wall
   c->r = r;
   c->wb = *bottom;
   c->wt = *top;
+  c->alpha_b = c->alpha_t = 1.0;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->plane = lay.plane;
   c->elem = elem_bytes(int(prec));
@@ -260,6 +264,10 @@ int create_common(lbm_lattice lattice, lbm_grid grid, double tau, const lbm_wall
 
   int st = device_status(
       c, hipMemcpyAsync(c->tab, &host_tab, sizeof(Tables), hipMemcpyHostToDevice, c->stream));
+  // zero both population buffers once, so that the padding at the end of
+  // each plane (never written by the kernels) holds no stale bytes and a
+  // checkpoint is a pure function of the state
+  if (st == LBM_OK) st = device_status(c, hipMemsetAsync(c->f[0], 0, 2 * pop_bytes, c->stream));
   if (st == LBM_OK) st = device_status(c, hipStreamSynchronize(c->stream));
   if (st == LBM_OK) st = run_init(c, nullptr);
   if (st != LBM_OK) {
@@ -604,6 +612,20 @@ int lbm_batch_step(lbm_ctx* const* ctxs, int n_ctx, int64_t k_steps, double* res
   std::vector<int64_t> budgets(n_ctx, k_steps);
   return lbm_batch_run(ctxs, n_ctx, budgets.data(), k_steps, -1.0, residuals_out, nullptr,
                        nullptr);
+}
+
+int lbm_set_accommodation(lbm_ctx* c, double alpha_bottom, double alpha_top) {
+  if (!c || !(alpha_bottom >= 0.0 && alpha_bottom <= 1.0) ||
+      !(alpha_top >= 0.0 && alpha_top <= 1.0))
+    return LBM_EINVAL;
+  c->alpha_b = alpha_bottom;
+  c->alpha_t = alpha_top;
+  Tables host_tab;
+  (void)fill_tables(c, &host_tab);  // walls unchanged: already checked at creation
+  int st = device_status(
+      c, hipMemcpyAsync(c->tab, &host_tab, sizeof(Tables), hipMemcpyHostToDevice, c->stream));
+  if (st == LBM_OK) st = device_status(c, hipStreamSynchronize(c->stream));
+  return st;
 }
 
 int lbm_set_timing(lbm_ctx* c, int enable) {

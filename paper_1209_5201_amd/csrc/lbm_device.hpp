@@ -287,9 +287,15 @@ __device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
 // output fields of the pre-collision state f~ at node n (Eq. (eq:summac)):
 // rho, u, T, and the stress and heat flux of the original f, obtained from
 // f~ by the conversion of Sec. II, f - f^eq = tau/(tau+1/2) (f~ - f^eq).
-// The stress / flux sums run over deviations only; their rest-state parts
-// are exact closed forms of the lattice's moments:
-//   sum_q w_q C_x C_y = u_x u_y,   sum_q w_q |C|^2 C_i = -u_i (D + 2 + |u|^2).
+// With C = c - u, sigma_xy = sum f C_x C_y and q_i = 1/2 sum f |C|^2 C_i.
+// The equilibrium parts are exact closed forms of the lattice's moments, so
+// only the small non-equilibrium part f~ - f^eq is summed (no cancellation
+// of O(u) terms in single precision):
+//   sum_q f^eq_q C_x C_y = 0 (second moments of f^eq are exact on every set);
+//   sum_q f^eq_q |C|^2 C_i = 0 on sets whose f^eq reproduces the third
+//   moments (fourth-order f^eq on D2Q17 and D3Q121).
+// D2Q16's second-order f^eq does not: its heat flux sums f - w and adds
+//   sum_q w_q |C|^2 C_i = -u_i (D + 2 + |u|^2).
 template <class L, class R, bool MOM = false>
 __device__ __forceinline__ void relax(R (&g)[L::Q], R omega, double kfac = 0.0,
                                       double* mom = nullptr, long long nodes = 0,
@@ -310,28 +316,35 @@ __device__ __forceinline__ void relax(R (&g)[L::Q], R omega, double kfac = 0.0,
     x = add_scaled<ez>(x, sz);
     const R geq = R(L::W[q]) * k.template poly<ex * ex + ey * ey + ez * ez>(x);
     if constexpr (MOM) {
-      const R fp = geq + kf * (g[q] - geq);  // deviation of f from w
+      const R neq = g[q] - geq;  // f~ - f^eq
       const R Cx = R(L::R * ex) - m.ux, Cy = R(L::R * ey) - m.uy, Cz = R(L::R * ez) - m.uz;
       const R C2 = Cx * Cx + Cy * Cy + Cz * Cz;
-      sxy += fp * Cx * Cy;
-      qx += fp * C2 * Cx;
-      qy += fp * C2 * Cy;
-      qz += fp * C2 * Cz;
+      sxy += neq * Cx * Cy;
+      const R fq = L::EQ >= 3 ? neq : geq + kf * neq;  // D2Q16: deviation of f from w
+      qx += fq * C2 * Cx;
+      qy += fq * C2 * Cy;
+      qz += fq * C2 * Cz;
     }
     g[q] = g[q] + omega * (geq - g[q]);
   };
   static_for<0, L::Q>(body);
   if constexpr (MOM) {
-    const R rest = -(R(L::D + 2) + uu);
     mom[0 * nodes + n] = 1.0 + double(m.drho);
     mom[1 * nodes + n] = double(m.ux);
     mom[2 * nodes + n] = double(m.uy);
     mom[3 * nodes + n] = double(m.uz);
     mom[4 * nodes + n] = 1.0 + double(m.th);
-    mom[5 * nodes + n] = double(m.ux * m.uy + sxy);
-    mom[6 * nodes + n] = 0.5 * double(m.ux * rest + qx);
-    mom[7 * nodes + n] = 0.5 * double(m.uy * rest + qy);
-    mom[8 * nodes + n] = 0.5 * double(m.uz * rest + qz);
+    mom[5 * nodes + n] = double(kf * sxy);
+    if constexpr (L::EQ >= 3) {
+      mom[6 * nodes + n] = 0.5 * double(kf * qx);
+      mom[7 * nodes + n] = 0.5 * double(kf * qy);
+      mom[8 * nodes + n] = 0.5 * double(kf * qz);
+    } else {
+      const R rest = -(R(L::D + 2) + uu);
+      mom[6 * nodes + n] = 0.5 * double(m.ux * rest + qx);
+      mom[7 * nodes + n] = 0.5 * double(m.uy * rest + qy);
+      mom[8 * nodes + n] = 0.5 * double(m.uz * rest + qz);
+    }
   }
 }
 
@@ -360,6 +373,15 @@ __device__ __forceinline__ void wrapped_columns(int x, int nx, int (&xw)[2 * NS 
     }
     xw[s + NS] = c;
   }
+}
+
+// Index of the velocity with the normal (y) component reversed.
+template <class L>
+constexpr int mirror_y(int q) {
+  for (int m = 0; m < L::Q; ++m)
+    if (L::E[m][0] == L::E[q][0] && L::E[m][1] == -L::E[q][1] && L::E[m][2] == L::E[q][2])
+      return m;
+  return -1;
 }
 
 template <class L>
@@ -451,9 +473,15 @@ __global__ __launch_bounds__(kBlock) void wall_kernel(StepArgs a) {
 
 // ------------------------------------------------------------- the step --
 // Pull of one node: f~_q(x, y) = f*_q(x - e_x, y - e_y), or, when the source
-// row lies in a ghost layer, the value the wall re-emits there:
-// g^eq_q(u_w, T_w) * (pooled mass / D) of the source's ghost column (read
-// through ratio(wall, q)).  Returns deviations from w_q.
+// row lies in a ghost layer, the value the wall re-emits there through the
+// scattering kernel R = a R_D + (1 - a) R_S of Sec. III:
+//  - diffuse share: a g^eq_q(u_w, T_w) * (pooled mass / D) of the source's
+//    ghost column (read through ratio(wall, q)), Eq. (eq:dkboundary);
+//  - specular share: (1 - a) times the population that a mirror at the wall
+//    plane maps onto the source, f*_{q'}(x - e_x, y'), q' = q with e_y
+//    reversed and y' the source row reflected (-1 - y_s below the bottom
+//    wall, 2 ny - 1 - y_s above the top one).
+// Returns deviations from w_q (w_q' = w_q).
 template <class L, class C, class Ratio>
 __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a, int y,
                                      const int (&xw)[2 * max_ex<L>() + 1], Ratio&& ratio) {
@@ -482,9 +510,28 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
       const int ys = y - ey;
       if (ey > 0 && ys < 0) {
         // re-emitted by the bottom wall: f = g^eq(u_b, T_b) M / D
-        f[q] = R(a.tab->gb[q] * ratio(0, ex) - L::W[q]);
+        double g = a.tab->gb[q] * ratio(0, ex) - L::W[q];
+        const double acc = a.tab->ab;
+        if (acc != 1.0) {
+          constexpr int m = mirror_y<L>(q);
+          static_assert(m >= 0, "velocity set not symmetric under y reversal");
+          const double gs = double(C::ld(fin, (uint32_t(-1 - ys) * nx + uint32_t(xw[ex + NS])) * C::B,
+                                          uint32_t(m) * pb, a.tab));
+          g = acc * g + (1.0 - acc) * gs;
+        }
+        f[q] = R(g);
       } else if (ey < 0 && ys >= a.ny) {
-        f[q] = R(a.tab->gt[q] * ratio(1, ex) - L::W[q]);  // top wall
+        double g = a.tab->gt[q] * ratio(1, ex) - L::W[q];  // top wall
+        const double acc = a.tab->at;
+        if (acc != 1.0) {
+          constexpr int m = mirror_y<L>(q);
+          static_assert(m >= 0, "velocity set not symmetric under y reversal");
+          const double gs = double(C::ld(
+              fin, (uint32_t(2 * a.ny - 1 - ys) * nx + uint32_t(xw[ex + NS])) * C::B,
+              uint32_t(m) * pb, a.tab));
+          g = acc * g + (1.0 - acc) * gs;
+        }
+        f[q] = R(g);
       } else {
         f[q] = C::ld(fin, (uint32_t(ys) * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(q) * pb,
                      a.tab);

@@ -25,6 +25,8 @@ struct Tables {
   double Db, Dt;      // sum over layers l and outgoing velocities of g^eq
   double Wb, Wt;      // rest-state part of the pooled mass: sum of w over the
                       // (velocity, row) pairs that cross each wall
+  double ab, at;      // accommodation of each wall: the diffuse share of the
+                      // scattering kernel R = a R_D + (1 - a) R_specular
   float dec;          // 16-bit codecs: g = h * dec
   float enc;          //                h = g * enc
   float pad[2];

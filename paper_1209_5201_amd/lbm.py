@@ -99,6 +99,7 @@ def _load():
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
                                          ctypes.c_double, _dp, ctypes.POINTER(ctypes.c_int64),
                                          _ip]),
+        "lbm_set_accommodation": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
         "lbm_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
         "lbm_kernel_time": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp,
                                            ctypes.POINTER(ctypes.c_int64)]),
@@ -119,7 +120,8 @@ def exported_symbols():
     return ["lbm_lattice_info", "lbm_tau_from_kn", "lbm_required_bytes", "lbm_create",
             "lbm_create_in", "lbm_init", "lbm_step", "lbm_field", "lbm_moments",
             "lbm_residual", "lbm_mass", "lbm_steps_done", "lbm_state_bytes", "lbm_save",
-            "lbm_load", "lbm_batch_step", "lbm_batch_run", "lbm_set_timing", "lbm_kernel_time", "lbm_destroy", "lbm_strerror",
+            "lbm_load", "lbm_batch_step", "lbm_batch_run", "lbm_set_accommodation",
+            "lbm_set_timing", "lbm_kernel_time", "lbm_destroy", "lbm_strerror",
             "lbm_last_device_error"]
 
 
@@ -269,6 +271,11 @@ def lbm_batch_run(ctxs, budgets, window: int, tol: float):
     return res, steps, state
 
 
+def lbm_set_accommodation(ctx, alpha_bottom: float, alpha_top: float):
+    _check(_load().lbm_set_accommodation(ctx, float(alpha_bottom), float(alpha_top)),
+           "lbm_set_accommodation")
+
+
 def lbm_set_timing(ctx, enable: bool):
     _check(_load().lbm_set_timing(ctx, int(bool(enable))), "lbm_set_timing")
 
@@ -295,7 +302,7 @@ class Channel:
     stream of `device`."""
 
     def __init__(self, lattice, nx, ny, tau, bottom=(0.0, 0.0, 1.0), top=(0.0, 0.0, 1.0),
-                 prec="fp64", device="cuda:0", kn=None):
+                 prec="fp64", device="cuda:0", kn=None, accommodation=(1.0, 1.0)):
         import torch
         self.lattice = lattice if isinstance(lattice, str) else \
             {v: k for k, v in LATTICES.items()}[lattice]
@@ -311,6 +318,11 @@ class Channel:
         self._stream = torch.cuda.current_stream(self.device)
         self.ctx = lbm_create_in(lattice, nx, ny, tau, bottom, top, prec,
                                  self._stream.cuda_stream, self._buf.data_ptr(), nbytes)
+        if tuple(accommodation) != (1.0, 1.0):
+            self.set_accommodation(*accommodation)
+
+    def set_accommodation(self, alpha_bottom: float, alpha_top: float):
+        lbm_set_accommodation(self.ctx, alpha_bottom, alpha_top)
 
     def init(self, rho=None, ux=None, uy=None, T=None):
         lbm_init(self.ctx, rho, ux, uy, T)

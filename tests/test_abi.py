@@ -101,3 +101,5 @@ def test_null_context_is_rejected():
     lib.lbm_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
     assert lib.lbm_step(None, 1) == lbm.lbm.LBM_EINVAL
     assert lbm.lbm_strerror(lbm.lbm.LBM_ENEGATIVE).startswith("wall Maxwellian")
+    lib.lbm_set_accommodation.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
+    assert lib.lbm_set_accommodation(None, 0.5, 0.5) == lbm.lbm.LBM_EINVAL
