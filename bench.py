@@ -166,7 +166,7 @@ def precision_table(torch, steps_2d: int = 200, steps_3d: int = 60):
             ("D2Q17", 2048, 2048, steps_2d, (W.C3["bottom"], W.C3["top"])),
             ("D3Q121", W.C5["nx"], W.C5["ny"], steps_3d, (W.C5["bottom"], W.C5["top"]))):
         Q = lbm.lbm_lattice_info(lat)["Q"]
-        for prec, b in (("fp64", 8), ("fp32", 4), ("bf16", 2), ("fp16", 2)):
+        for prec, b in (("fp64", 8), ("fp32", 4), ("fp32s", 4), ("bf16", 2), ("fp16", 2)):
             ch = lbm.Channel(lat, nx, ny, lbm.lbm_tau_from_kn(lat, ny, 0.05), *walls, prec=prec)
             ch.step(10)
             torch.cuda.synchronize()

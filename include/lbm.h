@@ -53,9 +53,20 @@ typedef enum { LBM_D2Q16 = 0, LBM_D2Q17 = 1, LBM_D3Q121 = 2 } lbm_lattice;
  * FP32: populations, moments, f^eq and relaxation in float.
  * BF16_DEV / FP16_DEV: populations stored as 16-bit (f - w_a) * S with a
  * per-format power-of-two S, decoded to float for all arithmetic.
+ * FP32_STORE: populations stored as float deviations f - w_a, rounded
+ * stochastically (a counter-based hash of node, velocity and step picks one
+ * of the two neighbouring floats, so results are reproducible); every
+ * arithmetic step in double.  The FP32 traffic, with single precision only
+ * in the stored values.
  * In every precision the wall sums, the wall ratio M/D, the output fields and
  * the mass / residual reductions are double. */
-typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_BF16_DEV = 2, LBM_FP16_DEV = 3 } lbm_precision;
+typedef enum {
+  LBM_FP64 = 0,
+  LBM_FP32 = 1,
+  LBM_BF16_DEV = 2,
+  LBM_FP16_DEV = 3,
+  LBM_FP32_STORE = 4
+} lbm_precision;
 
 typedef struct { int32_t nx, ny; } lbm_grid;
 

@@ -1,6 +1,7 @@
 // C ABI of the library (declared in include/lbm.h): argument checks, device
 // memory layout, the per-context wall tables, and the launch sequence of a
 // step.  All arithmetic of the scheme runs in the kernels.
+#include "batch_plan.hpp"
 #include "lbm.h"
 #include "lbm_internal.hpp"
 
@@ -50,7 +51,7 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-int elem_bytes(int prec) { return prec == kFP64 ? 8 : prec == kFP32 ? 4 : 2; }
+int elem_bytes(int prec) { return prec == kFP64 ? 8 : (prec == kFP32 || prec == kFP32S) ? 4 : 2; }
 
 struct Layout {
   size_t pop, ratio, tab, mom, snap, partial, result, total;
@@ -61,7 +62,7 @@ bool layout(int lattice, lbm_grid g, int prec, Layout* L) {
   int Q, D, N, EQ;
   double r;
   if (host_lattice(lattice, &Q, &D, &N, &EQ, &r, nullptr, nullptr) != 0) return false;
-  if (prec < 0 || prec > 3 || g.nx < 1 || g.ny < 2 * N) return false;
+  if (prec < 0 || prec >= kPrecCount || g.nx < 1 || g.ny < 2 * N) return false;
   const long long nodes = (long long)g.nx * g.ny;
   const long long plane = (nodes + 63) / 64 * 64;
   // the kernels address a plane set with 32-bit byte offsets
@@ -541,30 +542,25 @@ int lbm_batch_run(lbm_ctx* const* ctxs, int n_ctx, const int64_t* budgets, int64
   }
   // group the cases by storage format: one launch per format present
   std::vector<CaseDesc> desc(n_ctx);
-  std::vector<int> pos(n_ctx);
-  int start[5] = {0, 0, 0, 0, 0};
-  int m = 0;
-  for (int p = 0; p < 4; ++p) {
-    start[p] = m;
-    for (int i = 0; i < n_ctx; ++i) {
-      lbm_ctx* c = ctxs[i];
-      if (c->prec != p) continue;
-      CaseDesc& d = desc[m];
-      d.a = make_args(c, nullptr, nullptr, c->mom);
-      d.f[0] = c->f[0];
-      d.f[1] = c->f[1];
-      d.cur = c->cur;
-      d.snap = c->snap;
-      d.result = c->result;
-      d.uref = c->uref;
-      d.tol = tol;
-      d.lattice = c->lattice;
-      d.window = int(window);
-      d.budget = int(budgets[i] / window * window);
-      pos[i] = m++;
-    }
+  std::vector<int> pos(n_ctx), fmt(n_ctx);
+  int start[kPrecCount + 1] = {};
+  for (int i = 0; i < n_ctx; ++i) fmt[i] = ctxs[i]->prec;
+  if (!plan_groups(fmt.data(), n_ctx, kPrecCount, start, pos.data())) return LBM_EINVAL;
+  for (int i = 0; i < n_ctx; ++i) {
+    lbm_ctx* c = ctxs[i];
+    CaseDesc& d = desc[pos[i]];
+    d.a = make_args(c, nullptr, nullptr, c->mom);
+    d.f[0] = c->f[0];
+    d.f[1] = c->f[1];
+    d.cur = c->cur;
+    d.snap = c->snap;
+    d.result = c->result;
+    d.uref = c->uref;
+    d.tol = tol;
+    d.lattice = c->lattice;
+    d.window = int(window);
+    d.budget = int(budgets[i] / window * window);
   }
-  start[4] = m;
   const size_t desc_bytes = align256(sizeof(CaseDesc) * size_t(n_ctx));
   const size_t need = desc_bytes + sizeof(CaseOut) * size_t(n_ctx);
   std::vector<CaseOut> out(n_ctx);
@@ -583,9 +579,10 @@ int lbm_batch_run(lbm_ctx* const* ctxs, int n_ctx, const int64_t* budgets, int64
   if (!hip_ok(hipMemcpyAsync(ddesc, desc.data(), sizeof(CaseDesc) * size_t(n_ctx),
                              hipMemcpyHostToDevice, stream)))
     return LBM_EDEVICE;
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < kPrecCount; ++p) {
     const int cnt = start[p + 1] - start[p];
     if (cnt == 0) continue;
+    if (cnt < 0 || start[p] + cnt > n_ctx) return LBM_EINVAL;  // grouping is inconsistent
     if (!hip_ok(launch_batch(p, ddesc + start[p], cnt, dout + start[p], stream)))
       return LBM_EDEVICE;
   }

@@ -124,6 +124,40 @@ struct CF32 {
   }
 };
 
+// FP32 storage of the deviations, all arithmetic in double: the storage
+// rounding is the only single-precision error, at the traffic of FP32.  The
+// rounding is stochastic (to one of the two neighbouring floats, with
+// probability by distance): near a steady state a deterministic rounding
+// makes the same error at every step, a bias that the slow diffusive modes
+// accumulate over their relaxation time; unbiased rounding leaves noise.
+struct CF32S {
+  using S = float;
+  using R = double;
+  static constexpr uint32_t B = 4;
+  static constexpr bool kRandom = true;
+  __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
+    return double(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0)));
+  }
+  // In the float normal range add 29 random bits below the float's last
+  // significand bit to the double's magnitude and clear them: the result is
+  // a float, converted exactly.  Outside it (zero, tiny values) round to
+  // nearest.
+  template <int POL>
+  __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*,
+                            uint32_t rnd) {
+    uint64_t u = uint64_t(__double_as_longlong(g));
+    const uint64_t mag = u & 0x7fffffffffffffffull;
+    float f;
+    if (mag >= 0x3810000000000000ull && mag < 0x47efffffe0000000ull) {
+      u = (u + uint64_t(rnd & 0x1fffffffu)) & ~uint64_t(0x1fffffffu);
+      f = float(__longlong_as_double((long long)u));
+    } else {
+      f = float(g);
+    }
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(f), r, vo, so, POL);
+  }
+};
+
 struct CBF16 {
   using S = uint16_t;
   using R = float;
@@ -877,19 +911,23 @@ extern template hipError_t batch_launch<CF64>(const CaseDesc*, int, CaseOut*, hi
 extern template hipError_t batch_launch<CF32>(const CaseDesc*, int, CaseOut*, hipStream_t);
 extern template hipError_t batch_launch<CBF16>(const CaseDesc*, int, CaseOut*, hipStream_t);
 extern template hipError_t batch_launch<CFP16>(const CaseDesc*, int, CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF32S>(const CaseDesc*, int, CaseOut*, hipStream_t);
 
 extern template struct SetOps<D2Q16, CF64>;
 extern template struct SetOps<D2Q16, CF32>;
 extern template struct SetOps<D2Q16, CBF16>;
 extern template struct SetOps<D2Q16, CFP16>;
+extern template struct SetOps<D2Q16, CF32S>;
 extern template struct SetOps<D2Q17, CF64>;
 extern template struct SetOps<D2Q17, CF32>;
 extern template struct SetOps<D2Q17, CBF16>;
 extern template struct SetOps<D2Q17, CFP16>;
+extern template struct SetOps<D2Q17, CF32S>;
 extern template struct SetOps<D3Q121, CF64>;
 extern template struct SetOps<D3Q121, CF32>;
 extern template struct SetOps<D3Q121, CBF16>;
 extern template struct SetOps<D3Q121, CFP16>;
+extern template struct SetOps<D3Q121, CF32S>;
 
 }  // namespace dev
 }  // namespace lbm

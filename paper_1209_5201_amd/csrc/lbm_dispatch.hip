@@ -41,6 +41,7 @@ hipError_t by_prec(int prec, F&& fn) {
     case kFP32: return fn(dev::SetOps<L, dev::CF32>{});
     case kBF16: return fn(dev::SetOps<L, dev::CBF16>{});
     case kFP16: return fn(dev::SetOps<L, dev::CFP16>{});
+    case kFP32S: return fn(dev::SetOps<L, dev::CF32S>{});
   }
   return hipErrorInvalidValue;
 }
@@ -97,11 +98,13 @@ hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s) {
 
 hipError_t launch_batch(int prec, const CaseDesc* cases, int ncase, CaseOut* out,
                         hipStream_t s) {
+  if (ncase <= 0 || !cases || !out) return hipErrorInvalidValue;  // one workgroup per case
   switch (prec) {
     case kFP64: return dev::batch_launch<dev::CF64>(cases, ncase, out, s);
     case kFP32: return dev::batch_launch<dev::CF32>(cases, ncase, out, s);
     case kBF16: return dev::batch_launch<dev::CBF16>(cases, ncase, out, s);
     case kFP16: return dev::batch_launch<dev::CFP16>(cases, ncase, out, s);
+    case kFP32S: return dev::batch_launch<dev::CF32S>(cases, ncase, out, s);
   }
   return hipErrorInvalidValue;
 }

@@ -13,7 +13,8 @@ constexpr int kFields = 9;          // rho, ux, uy, uz, T, sxy, qx, qy, qz
 constexpr int kBlock = 256;         // threads per block of the node kernels
 constexpr int kReduceBlocks = 512;  // partial sums of the FP64 reductions
 
-enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2, kFP16 = 3 };
+enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2, kFP16 = 3, kFP32S = 4 };
+constexpr int kPrecCount = 5;
 
 // Per-context constants, resident in device memory and read by the kernels
 // through a const __restrict__ pointer (wave-uniform, so scalar loads).

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LATTICES = {"D2Q16": 0, "D2Q17": 1, "D3Q121": 2}
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "fp32s": 4}
 FIELDS = ("rho", "ux", "uy", "uz", "T", "sxy", "qx", "qy", "qz")
 
 LBM_OK = 0

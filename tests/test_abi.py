@@ -79,7 +79,9 @@ def test_required_bytes_and_limits():
     assert lbm.lbm_required_bytes("D2Q17", 1, 5, "fp64") == 0     # ny < 2N
     assert lbm.lbm_required_bytes("D2Q17", 0, 32, "fp64") == 0
     assert lbm.lbm_required_bytes("D3Q121", 1024, 1024, "bf16") < \
-        lbm.lbm_required_bytes("D3Q121", 1024, 1024, "fp32")
+        lbm.lbm_required_bytes("D3Q121", 1024, 1024, "fp32") == \
+        lbm.lbm_required_bytes("D3Q121", 1024, 1024, "fp32s")
+    assert lbm.lbm_required_bytes("D2Q17", 64, 64, 5) == 0    # no such format
 
 
 @pytest.mark.parametrize("kwargs", [
