@@ -507,15 +507,11 @@ __global__ __launch_bounds__(kBlock) void wall_kernel(StepArgs a) {
 
 // ------------------------------------------------------------- the step --
 // Pull of one node: f~_q(x, y) = f*_q(x - e_x, y - e_y), or, when the source
-// row lies in a ghost layer, the value the wall re-emits there through the
-// scattering kernel R = a R_D + (1 - a) R_S of Sec. III:
-//  - diffuse share: a g^eq_q(u_w, T_w) * (pooled mass / D) of the source's
-//    ghost column (read through ratio(wall, q)), Eq. (eq:dkboundary);
-//  - specular share: (1 - a) times the population that a mirror at the wall
-//    plane maps onto the source, f*_{q'}(x - e_x, y'), q' = q with e_y
-//    reversed and y' the source row reflected (-1 - y_s below the bottom
-//    wall, 2 ny - 1 - y_s above the top one).
-// Returns deviations from w_q (w_q' = w_q).
+// row lies in a ghost layer, the value the wall re-emits there:
+// g^eq_q(u_w, T_w) * (pooled mass / D) of the source's ghost column (read
+// through ratio(wall, q)), Eq. (eq:dkboundary).  Returns deviations from w_q.
+// A wall with accommodation below one also reflects part of the incoming
+// mass specularly; wall_specular adds that share afterwards.
 template <class L, class C, class Ratio>
 __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a, int y,
                                      const int (&xw)[2 * max_ex<L>() + 1], Ratio&& ratio) {
@@ -544,28 +540,9 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
       const int ys = y - ey;
       if (ey > 0 && ys < 0) {
         // re-emitted by the bottom wall: f = g^eq(u_b, T_b) M / D
-        double g = a.tab->gb[q] * ratio(0, ex) - L::W[q];
-        const double acc = a.tab->ab;
-        if (acc != 1.0) {
-          constexpr int m = mirror_y<L>(q);
-          static_assert(m >= 0, "velocity set not symmetric under y reversal");
-          const double gs = double(C::ld(fin, (uint32_t(-1 - ys) * nx + uint32_t(xw[ex + NS])) * C::B,
-                                          uint32_t(m) * pb, a.tab));
-          g = acc * g + (1.0 - acc) * gs;
-        }
-        f[q] = R(g);
+        f[q] = R(a.tab->gb[q] * ratio(0, ex) - L::W[q]);
       } else if (ey < 0 && ys >= a.ny) {
-        double g = a.tab->gt[q] * ratio(1, ex) - L::W[q];  // top wall
-        const double acc = a.tab->at;
-        if (acc != 1.0) {
-          constexpr int m = mirror_y<L>(q);
-          static_assert(m >= 0, "velocity set not symmetric under y reversal");
-          const double gs = double(C::ld(
-              fin, (uint32_t(2 * a.ny - 1 - ys) * nx + uint32_t(xw[ex + NS])) * C::B,
-              uint32_t(m) * pb, a.tab));
-          g = acc * g + (1.0 - acc) * gs;
-        }
-        f[q] = R(g);
+        f[q] = R(a.tab->gt[q] * ratio(1, ex) - L::W[q]);  // top wall
       } else {
         f[q] = C::ld(fin, (uint32_t(ys) * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(q) * pb,
                      a.tab);
@@ -573,6 +550,44 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
     };
     static_for<0, L::Q>(body);
   }
+}
+
+// Maxwell-type scattering at the walls (Sec. III's generic kernel R taken as
+// a R_D + (1 - a) R_S, a the wall's accommodation): for the velocities a
+// wall re-emits into row y, mix the diffuse value pull() produced with the
+// specular image, f~_q = a f_D + (1 - a) f*_{q'}(x - e_x, y'), q' = q with
+// e_y reversed and y' the source row reflected at the wall plane (-1 - y_s
+// below the bottom wall, 2 ny - 1 - y_s above the top one).  Does nothing
+// away from the walls or for a = 1 (the paper's diffuse wall).
+template <class L, class C>
+__device__ __forceinline__ void wall_specular(typename C::R (&f)[L::Q], const StepArgs& a, int y,
+                                              const int (&xw)[2 * max_ex<L>() + 1]) {
+  using R = typename C::R;
+  constexpr int NS = max_ex<L>();
+  const double ab = a.tab->ab, at = a.tab->at;
+  const bool bottom = y < L::N && ab != 1.0, top = y >= a.ny - L::N && at != 1.0;
+  if (!bottom && !top) return;
+  const Rsrc fin = plane_set<L, C>(a.fin, a.plane);
+  const uint32_t nx = uint32_t(a.nx);
+  const uint32_t pb = uint32_t(a.plane) * C::B;
+  auto body = [&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int ex = L::E[q][0], ey = L::E[q][1];
+    constexpr int m = mirror_y<L>(q);
+    static_assert(m >= 0, "velocity set not symmetric under y reversal");
+    const int ys = y - ey;
+    if (ey > 0 && ys < 0 && bottom) {
+      const double gs = double(C::ld(fin, (uint32_t(-1 - ys) * nx + uint32_t(xw[ex + NS])) * C::B,
+                                     uint32_t(m) * pb, a.tab));
+      f[q] = R(ab * double(f[q]) + (1.0 - ab) * gs);
+    } else if (ey < 0 && ys >= a.ny && top) {
+      const double gs = double(C::ld(
+          fin, (uint32_t(2 * a.ny - 1 - ys) * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(m) * pb,
+          a.tab));
+      f[q] = R(at * double(f[q]) + (1.0 - at) * gs);
+    }
+  };
+  static_for<0, L::Q>(body);
 }
 
 template <class L, class C, int POL = kStoreNT>
@@ -628,6 +643,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
   R f[L::Q];
   pull<L, C>(f, a, y, xw,
              [&](int wall, int ex) { return a.ratio[wall * a.nx + xw[ex + NS]]; });
+  wall_specular<L, C>(f, a, y, xw);
   relax<L, R, MOM>(f, R(a.omega), a.kfac, a.mom, nodes, n);
   store<L, C>(f, a, uint32_t(n));
 }
@@ -664,6 +680,7 @@ __global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
   R f[L::Q];
   pull<L, C>(f, a, y, xw,
              [&](int, int ex) { return ratio_s[int(threadIdx.x) - ex + NS]; });
+  if (bottom || top) wall_specular<L, C>(f, a, y, xw);
   const long long nodes = (long long)a.nx * a.ny;
   const uint32_t n = uint32_t(y) * uint32_t(a.nx) + uint32_t(x);
   relax<L, R, MOM>(f, R(a.omega), a.kfac, a.mom, nodes, n);
@@ -784,6 +801,7 @@ __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, doubl
         R f[L::Q];
         pull<L, C>(f, a, y, xw,
                    [&](int wall, int ex) { return ratio_s[wall * a.nx + xw[ex + NS]]; });
+        wall_specular<L, C>(f, a, y, xw);
         if (last)
           relax<L, R, true>(f, R(a.omega), a.kfac, a.mom, nodes, n);
         else
