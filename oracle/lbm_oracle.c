@@ -123,9 +123,21 @@ static int wrap(int x, int nx)
     return m < 0 ? m + nx : m;
 }
 
+/* Relaxation time of one node.  Constant tau (law == NULL) or, for thermal
+ * problems (end of Sec. II: tau may follow the local temperature), the
+ * non-dimensional tau = mu / p of Sec. II with p = rho T and a power-law
+ * viscosity mu = T^omega_v: tau_node = tau * T^(omega_v - 1) / rho, tau
+ * being the value at rho = T = 1.  law[0] = omega_v. */
+static double node_tau(double tau, const double *law, double rho, double T)
+{
+    if (!law)
+        return tau;
+    return tau * pow(T, law[0] - 1.0) / rho;
+}
+
 /* One full step.  flux (may be NULL) receives, summed over all ghost
  * columns: incoming and outgoing mass of the bottom wall, then of the top. */
-static void one_step(const olat *L, int nx, int ny, double omega,
+static void one_step(const olat *L, int nx, int ny, double tau, const double *law,
                      const double *gb, const double *gt,
                      double alpha_b, double alpha_t, const int *mirror,
                      double *f, double *fs, double *fn,
@@ -139,10 +151,12 @@ static void one_step(const olat *L, int nx, int ny, double omega,
     size_t n;
     int x, y, a, l;
 
-    /* 1-2. collision at every fluid node */
+    /* 1-2. collision at every fluid node, Eq. (eq:scheme) with the node's
+     * relaxation time */
     for (n = 0; n < nodes; ++n) {
-        double rho, u[3], T;
+        double rho, u[3], T, omega;
         node_moments(L, f + n * Q, &rho, u, &T);
+        omega = 1.0 / (node_tau(tau, law, rho, T) + 0.5);
         for (a = 0; a < Q; ++a) {
             double feq = rho * geq(L, a, u, T);
             fs[n * Q + a] = f[n * Q + a] - omega * (f[n * Q + a] - feq);
@@ -287,17 +301,18 @@ void orc_init(int Q, int D, int eq_order, int thermal, const int *e,
  * (tangential velocities only); alpha_b/alpha_t their accommodation (1:
  * diffuse, Eq. (eq:dkboundary); 0: specular).  tau is the relaxation time in
  * time steps; +inf gives the collisionless limit.  flux (may be NULL): 4
- * doubles per step, see one_step().  Returns 0, -1 on allocation failure,
+ * doubles per step, see one_step().  law (may be NULL): the viscosity law
+ * of node_tau().  Returns 0, -1 on allocation failure,
  * -2 if a velocity has no mirror image in the set. */
 int orc_run(int Q, int D, int eq_order, int thermal, const int *e,
             const double *w, double r, int nx, int ny, double tau,
             const double *wall_b, const double *wall_t, double alpha_b,
-            double alpha_t, double *f, long nsteps, double *flux)
+            double alpha_t, double *f, long nsteps, double *flux,
+            const double *law)
 {
     olat L = {Q, D, eq_order, thermal, e, w, r};
     const int N = max_ey(&L);
     const size_t nodes = (size_t)nx * (size_t)ny;
-    double omega = 1.0 / (tau + 0.5);
     double ub[3] = {wall_b[0], 0.0, wall_b[1]};
     double ut[3] = {wall_t[0], 0.0, wall_t[1]};
     double *gb = malloc(Q * sizeof(double));
@@ -333,7 +348,7 @@ int orc_run(int Q, int D, int eq_order, int thermal, const int *e,
         }
     }
     for (s = 0; s < nsteps; ++s)
-        one_step(&L, nx, ny, omega, gb, gt, alpha_b, alpha_t, mirror, f, fs, fn,
+        one_step(&L, nx, ny, tau, law, gb, gt, alpha_b, alpha_t, mirror, f, fs, fn,
                  ghb, ght, gob, got, flux ? flux + 4 * s : NULL);
 done:
     free(gb);
@@ -349,24 +364,26 @@ done:
 }
 
 /* Output fields of f~ at one time level (Eq. (eq:summac)).  The stress and
- * heat flux of the original f follow from f - f^eq = (f~ - f^eq) tau/(tau+1/2)
+ * heat flux of the original f follow from f - f^eq = (f~ - f^eq) tau/(tau+1/2),
+ * tau the node's relaxation time (node_tau)
  * (the change of variable of Sec. II); the moments are linear in f, so
  *   X[f] = X[f^eq] + tau/(tau + 1/2) (X[f~] - X[f^eq]).
  * out: 9 fields of nx*ny: rho, ux, uy, uz, T, sigma_xy, q_x, q_y, q_z. */
 void orc_moments(int Q, int D, int eq_order, int thermal, const int *e,
                  const double *w, double r, int nx, int ny, double tau,
-                 const double *f, double *out)
+                 const double *f, double *out, const double *law)
 {
     olat L = {Q, D, eq_order, thermal, e, w, r};
     const size_t nodes = (size_t)nx * (size_t)ny;
-    double k = isinf(tau) ? 1.0 : tau / (tau + 0.5);
     size_t n;
     int a, i;
     for (n = 0; n < nodes; ++n) {
         const double *fn = f + n * Q;
-        double rho, u[3], T;
+        double rho, u[3], T, tn, k;
         double sig_t = 0.0, sig_e = 0.0, q_t[3] = {0, 0, 0}, q_e[3] = {0, 0, 0};
         node_moments(&L, fn, &rho, u, &T);
+        tn = node_tau(tau, law, rho, T);
+        k = isinf(tn) ? 1.0 : tn / (tn + 0.5);
         for (a = 0; a < Q; ++a) {
             double C[3], C2 = 0.0, feq = rho * geq(&L, a, u, T);
             for (i = 0; i < 3; ++i) {
