@@ -204,6 +204,19 @@ int lbm_batch_run(lbm_ctx *const *ctxs, int n_ctx, const int64_t *budgets, int64
  * Synchronizes the context stream. */
 int lbm_set_accommodation(lbm_ctx *ctx, double alpha_bottom, double alpha_top);
 
+/* Local relaxation time for thermal problems (end of Sec. II: tau may
+ * follow the local gas temperature).  With enable != 0 every node relaxes
+ * with tau_node = tau * T^(w - 1) / rho, the non-dimensional tau = mu / p
+ * of Sec. II for p = rho T and a power-law viscosity mu = T^w (w = exponent;
+ * 1/2 hard spheres, 1 Maxwell molecules), tau being the value given to
+ * lbm_create (its value at rho = T = 1); the stress and heat flux
+ * conversion uses each node's tau.  enable = 0 restores constant tau (the
+ * default, the paper's runs).  Requires the thermal set (LBM_D3Q121), a
+ * finite tau and |w| <= 4, else LBM_EINVAL and nothing changes.  Host-only.
+ * The state after lbm_step holds the populations after the collision of
+ * the last step, so the law governs the collisions of later steps. */
+int lbm_set_viscosity_law(lbm_ctx *ctx, int enable, double exponent);
+
 /* Kernel timing with HIP events (profiling aid).  While enabled, lbm_step
  * brackets every launch of the wall-sum kernel and of the fused update kernel
  * with events on the context stream and accumulates their durations; the

@@ -22,6 +22,8 @@ struct lbm_ctx {
   double tau, r;
   lbm_wall wb, wt;
   double alpha_b, alpha_t;  // accommodation (1: the paper's diffuse wall)
+  int law;                  // 1: local tau from the viscosity law
+  double vexp;              // its exponent w
   hipStream_t stream;
   bool owns;
   char* base;
@@ -121,6 +123,9 @@ StepArgs make_args(lbm_ctx* c, const void* fin, void* fout, double* mom) {
   a.plane = c->plane;
   a.omega = 1.0 / (c->tau + 0.5);
   a.kfac = std::isinf(c->tau) ? 1.0 : c->tau / (c->tau + 0.5);
+  a.tau = c->tau;
+  a.vexp = c->vexp;
+  a.law = c->law;
   a.step = uint32_t(c->steps);
   a.seed = 0x2545f491u;
   return a;
@@ -623,6 +628,21 @@ int lbm_set_accommodation(lbm_ctx* c, double alpha_bottom, double alpha_top) {
       c, hipMemcpyAsync(c->tab, &host_tab, sizeof(Tables), hipMemcpyHostToDevice, c->stream));
   if (st == LBM_OK) st = device_status(c, hipStreamSynchronize(c->stream));
   return st;
+}
+
+int lbm_set_viscosity_law(lbm_ctx* c, int enable, double exponent) {
+  if (!c) return LBM_EINVAL;
+  if (enable) {
+    if (c->lattice != LBM_D3Q121 || !std::isfinite(c->tau) || !std::isfinite(exponent) ||
+        std::fabs(exponent) > 4.0)
+      return LBM_EINVAL;
+    c->law = 1;
+    c->vexp = exponent;
+  } else {
+    c->law = 0;
+    c->vexp = 0.0;
+  }
+  return LBM_OK;
 }
 
 int lbm_set_timing(lbm_ctx* c, int enable) {

@@ -331,15 +331,22 @@ __device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
 // D2Q16's second-order f^eq does not: its heat flux sums f - w and adds
 //   sum_q w_q |C|^2 C_i = -u_i (D + 2 + |u|^2).
 template <class L, class R, bool MOM = false>
-__device__ __forceinline__ void relax(R (&g)[L::Q], R omega, double kfac = 0.0,
-                                      double* mom = nullptr, long long nodes = 0,
-                                      long long n = 0) {
+__device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* mom = nullptr,
+                                      long long nodes = 0, long long n = 0) {
   const Macro<R> m = macro<L, R>(g);
   const R uu = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
   const auto k = EqCoef<L, R>::make(m.rho, m.drho, uu, m.th);
   constexpr R r = R(L::R);
   const R sx = r * m.ux, sy = r * m.uy, sz = r * m.uz;
-  const R kf = R(kfac);
+  R omega = R(a.omega), kf = R(a.kfac);
+  if constexpr (L::THERMAL) {
+    if (a.law) {
+      // local relaxation time tau = mu / p (Sec. II) with mu = T^w, p = rho T
+      const R tn = R(a.tau) * pow(R(1) + m.th, R(a.vexp) - R(1)) / m.rho;
+      omega = R(1) / (tn + R(0.5));
+      kf = tn * omega;
+    }
+  }
   R sxy = 0, qx = 0, qy = 0, qz = 0;
   auto body = [&](auto qc) {
     constexpr int q = decltype(qc)::value;
@@ -644,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
   pull<L, C>(f, a, y, xw,
              [&](int wall, int ex) { return a.ratio[wall * a.nx + xw[ex + NS]]; });
   wall_specular<L, C>(f, a, y, xw);
-  relax<L, R, MOM>(f, R(a.omega), a.kfac, a.mom, nodes, n);
+  relax<L, R, MOM>(f, a, a.mom, nodes, n);
   store<L, C>(f, a, uint32_t(n));
 }
 
@@ -683,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
   if (bottom || top) wall_specular<L, C>(f, a, y, xw);
   const long long nodes = (long long)a.nx * a.ny;
   const uint32_t n = uint32_t(y) * uint32_t(a.nx) + uint32_t(x);
-  relax<L, R, MOM>(f, R(a.omega), a.kfac, a.mom, nodes, n);
+  relax<L, R, MOM>(f, a, a.mom, nodes, n);
   store<L, C>(f, a, n);
 }
 
@@ -714,7 +721,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double* 
     f[q] = R(L::W[q] * k.template poly<ex * ex + ey * ey + ez * ez>(x));  // f^eq - w
   };
   static_for<0, L::Q>(body);
-  relax<L, R, true>(f, R(a.omega), a.kfac, a.mom, nodes, n);
+  relax<L, R, true>(f, a, a.mom, nodes, n);
   store<L, C>(f, a, uint32_t(n));
 }
 
@@ -803,9 +810,9 @@ __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, doubl
                    [&](int wall, int ex) { return ratio_s[wall * a.nx + xw[ex + NS]]; });
         wall_specular<L, C>(f, a, y, xw);
         if (last)
-          relax<L, R, true>(f, R(a.omega), a.kfac, a.mom, nodes, n);
+          relax<L, R, true>(f, a, a.mom, nodes, n);
         else
-          relax<L, R>(f, R(a.omega));
+          relax<L, R>(f, a);
         store<L, C, kStoreCached>(f, a, uint32_t(n));
       }
       __syncthreads();

@@ -43,6 +43,9 @@ struct StepArgs {
   long long plane;      // elements between population planes
   double omega;         // 1 / (tau + 1/2)
   double kfac;          // tau / (tau + 1/2): f~ -> f conversion of sigma, q
+  double tau;           // relaxation time at rho = T = 1
+  double vexp;          // viscosity exponent w of the local law (law != 0)
+  int law;              // 0: constant tau; 1: tau T^(w-1) / rho per node
   uint32_t step;        // index of the step being produced (rounding counter)
   uint32_t seed;        // per-context rounding seed
 };

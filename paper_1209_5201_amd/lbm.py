@@ -100,6 +100,7 @@ def _load():
                                          ctypes.c_double, _dp, ctypes.POINTER(ctypes.c_int64),
                                          _ip]),
         "lbm_set_accommodation": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
+        "lbm_set_viscosity_law": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double]),
         "lbm_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
         "lbm_kernel_time": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp,
                                            ctypes.POINTER(ctypes.c_int64)]),
@@ -121,7 +122,7 @@ def exported_symbols():
             "lbm_create_in", "lbm_init", "lbm_step", "lbm_field", "lbm_moments",
             "lbm_residual", "lbm_mass", "lbm_steps_done", "lbm_state_bytes", "lbm_save",
             "lbm_load", "lbm_batch_step", "lbm_batch_run", "lbm_set_accommodation",
-            "lbm_set_timing", "lbm_kernel_time", "lbm_destroy", "lbm_strerror",
+            "lbm_set_viscosity_law", "lbm_set_timing", "lbm_kernel_time", "lbm_destroy", "lbm_strerror",
             "lbm_last_device_error"]
 
 
@@ -276,6 +277,13 @@ def lbm_set_accommodation(ctx, alpha_bottom: float, alpha_top: float):
            "lbm_set_accommodation")
 
 
+def lbm_set_viscosity_law(ctx, exponent):
+    """exponent w of mu = T^w for the local relaxation time; None: constant tau."""
+    _check(_load().lbm_set_viscosity_law(ctx, int(exponent is not None),
+                                         0.0 if exponent is None else float(exponent)),
+           "lbm_set_viscosity_law")
+
+
 def lbm_set_timing(ctx, enable: bool):
     _check(_load().lbm_set_timing(ctx, int(bool(enable))), "lbm_set_timing")
 
@@ -302,7 +310,8 @@ class Channel:
     stream of `device`."""
 
     def __init__(self, lattice, nx, ny, tau, bottom=(0.0, 0.0, 1.0), top=(0.0, 0.0, 1.0),
-                 prec="fp64", device="cuda:0", kn=None, accommodation=(1.0, 1.0)):
+                 prec="fp64", device="cuda:0", kn=None, accommodation=(1.0, 1.0),
+                 viscosity_exp=None):
         import torch
         self.lattice = lattice if isinstance(lattice, str) else \
             {v: k for k, v in LATTICES.items()}[lattice]
@@ -320,6 +329,11 @@ class Channel:
                                  self._stream.cuda_stream, self._buf.data_ptr(), nbytes)
         if tuple(accommodation) != (1.0, 1.0):
             self.set_accommodation(*accommodation)
+        if viscosity_exp is not None:
+            self.set_viscosity_law(viscosity_exp)
+
+    def set_viscosity_law(self, exponent):
+        lbm_set_viscosity_law(self.ctx, exponent)
 
     def set_accommodation(self, alpha_bottom: float, alpha_top: float):
         lbm_set_accommodation(self.ctx, alpha_bottom, alpha_top)
