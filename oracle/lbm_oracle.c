@@ -77,6 +77,42 @@ static double geq(const olat *L, int a, const double u[3], double T)
     return L->w[a] * g;
 }
 
+/* Body force (not in the paper; a constant acceleration a of every node).
+ * The force term of the Boltzmann equation, -a . grad_c f, projected on the
+ * Hermite polynomials up to the equilibrium's order N equals the
+ * directional derivative of the truncated equilibrium in u at fixed rho and
+ * T: F_a = a . d f^eq_a / du.  Here the printed terms of Eq. (eq:feq) are
+ * differentiated one by one (d(c.u) = a.c, d(u.u) = 2 a.u); unit density. */
+static double force_term(const olat *L, int a, const double u[3], double T,
+                         const double acc[3])
+{
+    double c[3], cu = 0.0, uu = 0.0, cc = 0.0, ca = 0.0, au = 0.0;
+    double D = (double)L->D;
+    double th = T - 1.0;
+    double d;
+    int i;
+    for (i = 0; i < 3; ++i) {
+        c[i] = L->r * (double)L->e[3 * a + i];
+        cu += c[i] * u[i];
+        uu += u[i] * u[i];
+        cc += c[i] * c[i];
+        ca += c[i] * acc[i];
+        au += acc[i] * u[i];
+    }
+    d = ca;
+    if (L->eq_order >= 2)
+        d += 0.5 * (2.0 * cu * ca - 2.0 * au);
+    if (L->eq_order >= 3)
+        d += ca / 6.0 * (cu * cu - 3.0 * uu + 3.0 * th * (cc - D - 2.0)) +
+             cu / 6.0 * (2.0 * cu * ca - 6.0 * au);
+    if (L->eq_order >= 4) {
+        d += (4.0 * cu * cu * cu * ca - 6.0 * (2.0 * cu * ca * uu + cu * cu * 2.0 * au) +
+              3.0 * 2.0 * uu * 2.0 * au) / 24.0;
+        d += th / 4.0 * ((cc - D - 2.0) * (2.0 * cu * ca - 2.0 * au) - 4.0 * cu * ca);
+    }
+    return L->w[a] * d;
+}
+
 /* Eq. (eq:summac): density, velocity and temperature of one node.
  * Isothermal lattices use T = 1 (Sec. II, after Eq. (eq:feq)). */
 static void node_moments(const olat *L, const double *f, double *rho,
@@ -106,6 +142,26 @@ static void node_moments(const olat *L, const double *f, double *rho,
     } else {
         *T = 1.0;
     }
+}
+
+/* Moments of the physical f from the stored f~ (Sec. II change of
+ * variable, extended by the force: f = f~ + J/2 with J = -(f - f^eq)/tau + F,
+ * whose mass and energy moments over J's collision part vanish):
+ *   rho = sum f~,  rho u = sum f~ c + rho a / 2,
+ *   rho D T = sum f~ |c|^2 + rho a.u - rho u^2, i.e. T = T[f~] + a^2/(4D).
+ * acc == NULL: no force, the moments of f~ itself. */
+static void phys_moments(const olat *L, const double *f, const double *acc,
+                         double *rho, double u[3], double *T)
+{
+    int i;
+    node_moments(L, f, rho, u, T);
+    if (!acc)
+        return;
+    for (i = 0; i < 3; ++i)
+        u[i] += 0.5 * acc[i];
+    if (L->thermal)
+        *T += (acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]) /
+              (4.0 * (double)L->D);
 }
 
 static int max_ey(const olat *L)
@@ -138,6 +194,7 @@ static double node_tau(double tau, const double *law, double rho, double T)
 /* One full step.  flux (may be NULL) receives, summed over all ghost
  * columns: incoming and outgoing mass of the bottom wall, then of the top. */
 static void one_step(const olat *L, int nx, int ny, double tau, const double *law,
+                     const double *acc,
                      const double *gb, const double *gt,
                      double alpha_b, double alpha_t, const int *mirror,
                      double *f, double *fs, double *fn,
@@ -152,14 +209,21 @@ static void one_step(const olat *L, int nx, int ny, double tau, const double *la
     int x, y, a, l;
 
     /* 1-2. collision at every fluid node, Eq. (eq:scheme) with the node's
-     * relaxation time */
+     * relaxation time; with a force, the trapezoidal rule of Sec. II applied
+     * to J = -(f - f^eq)/tau + F gives
+     *   f*~ = f~ - (f~ - f^eq)/(tau + 1/2) + tau/(tau + 1/2) F
+     * with f^eq and F at the moments of f (phys_moments). */
     for (n = 0; n < nodes; ++n) {
-        double rho, u[3], T, omega;
-        node_moments(L, f + n * Q, &rho, u, &T);
-        omega = 1.0 / (node_tau(tau, law, rho, T) + 0.5);
+        double rho, u[3], T, tn, omega;
+        phys_moments(L, f + n * Q, acc, &rho, u, &T);
+        tn = node_tau(tau, law, rho, T);
+        omega = 1.0 / (tn + 0.5);
         for (a = 0; a < Q; ++a) {
             double feq = rho * geq(L, a, u, T);
             fs[n * Q + a] = f[n * Q + a] - omega * (f[n * Q + a] - feq);
+            if (acc)
+                fs[n * Q + a] += (isinf(tn) ? 1.0 : tn * omega) * rho *
+                                 force_term(L, a, u, T, acc);
         }
     }
 
@@ -302,13 +366,14 @@ void orc_init(int Q, int D, int eq_order, int thermal, const int *e,
  * diffuse, Eq. (eq:dkboundary); 0: specular).  tau is the relaxation time in
  * time steps; +inf gives the collisionless limit.  flux (may be NULL): 4
  * doubles per step, see one_step().  law (may be NULL): the viscosity law
- * of node_tau().  Returns 0, -1 on allocation failure,
+ * of node_tau().  acc (may be NULL): body force, 3 components of the
+ * acceleration per time step (see force_term()).  Returns 0, -1 on allocation failure,
  * -2 if a velocity has no mirror image in the set. */
 int orc_run(int Q, int D, int eq_order, int thermal, const int *e,
             const double *w, double r, int nx, int ny, double tau,
             const double *wall_b, const double *wall_t, double alpha_b,
             double alpha_t, double *f, long nsteps, double *flux,
-            const double *law)
+            const double *law, const double *acc)
 {
     olat L = {Q, D, eq_order, thermal, e, w, r};
     const int N = max_ey(&L);
@@ -348,7 +413,7 @@ int orc_run(int Q, int D, int eq_order, int thermal, const int *e,
         }
     }
     for (s = 0; s < nsteps; ++s)
-        one_step(&L, nx, ny, tau, law, gb, gt, alpha_b, alpha_t, mirror, f, fs, fn,
+        one_step(&L, nx, ny, tau, law, acc, gb, gt, alpha_b, alpha_t, mirror, f, fs, fn,
                  ghb, ght, gob, got, flux ? flux + 4 * s : NULL);
 done:
     free(gb);
@@ -365,13 +430,15 @@ done:
 
 /* Output fields of f~ at one time level (Eq. (eq:summac)).  The stress and
  * heat flux of the original f follow from f - f^eq = (f~ - f^eq) tau/(tau+1/2),
- * tau the node's relaxation time (node_tau)
+ * tau the node's relaxation time (node_tau), with f~ + F/2 in place of f~
+ * under a body force
  * (the change of variable of Sec. II); the moments are linear in f, so
  *   X[f] = X[f^eq] + tau/(tau + 1/2) (X[f~] - X[f^eq]).
  * out: 9 fields of nx*ny: rho, ux, uy, uz, T, sigma_xy, q_x, q_y, q_z. */
 void orc_moments(int Q, int D, int eq_order, int thermal, const int *e,
                  const double *w, double r, int nx, int ny, double tau,
-                 const double *f, double *out, const double *law)
+                 const double *f, double *out, const double *law,
+                 const double *acc)
 {
     olat L = {Q, D, eq_order, thermal, e, w, r};
     const size_t nodes = (size_t)nx * (size_t)ny;
@@ -381,20 +448,22 @@ void orc_moments(int Q, int D, int eq_order, int thermal, const int *e,
         const double *fn = f + n * Q;
         double rho, u[3], T, tn, k;
         double sig_t = 0.0, sig_e = 0.0, q_t[3] = {0, 0, 0}, q_e[3] = {0, 0, 0};
-        node_moments(&L, fn, &rho, u, &T);
+        phys_moments(&L, fn, acc, &rho, u, &T);
         tn = node_tau(tau, law, rho, T);
         k = isinf(tn) ? 1.0 : tn / (tn + 0.5);
         for (a = 0; a < Q; ++a) {
             double C[3], C2 = 0.0, feq = rho * geq(&L, a, u, T);
+            /* with a force, f - f^eq = tau/(tau+1/2) (f~ + F/2 - f^eq) */
+            double ft = fn[a] + (acc ? 0.5 * rho * force_term(&L, a, u, T, acc) : 0.0);
             for (i = 0; i < 3; ++i) {
                 C[i] = L.r * (double)L.e[3 * a + i] - u[i];
                 C2 += C[i] * C[i];
             }
             /* the xy entry of the trace-free tensor C<i C j> is C_x C_y */
-            sig_t += fn[a] * C[0] * C[1];
+            sig_t += ft * C[0] * C[1];
             sig_e += feq * C[0] * C[1];
             for (i = 0; i < 3; ++i) {
-                q_t[i] += 0.5 * fn[a] * C2 * C[i];
+                q_t[i] += 0.5 * ft * C2 * C[i];
                 q_e[i] += 0.5 * feq * C2 * C[i];
             }
         }

@@ -55,10 +55,10 @@ def _load():
             lib.orc_init.restype = None
             lib.orc_run.argtypes = lat + [ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double, _dp, _dp, ctypes.c_double,
-                                          ctypes.c_double, _dp, ctypes.c_long, _dp, _dp]
+                                          ctypes.c_double, _dp, ctypes.c_long, _dp, _dp, _dp]
             lib.orc_run.restype = ctypes.c_int
             lib.orc_moments.argtypes = lat + [ctypes.c_int, ctypes.c_int,
-                                              ctypes.c_double, _dp, _dp, _dp]
+                                              ctypes.c_double, _dp, _dp, _dp, _dp]
             lib.orc_moments.restype = None
             _lib = lib
     return _lib
@@ -115,14 +115,16 @@ class OracleCase:
     kernel (1: fully diffuse, the paper's wall).  Initial fields default to
     rho = 1, u = 0, T = 1.  viscosity_exp = omega_v switches to the local
     relaxation time tau T^(omega_v - 1) / rho (mu = T^omega_v, p = rho T);
-    None keeps tau constant.
+    None keeps tau constant.  force = (a_x, a_y, a_z): a body force, the
+    acceleration of every node per time step (None: no force).
     """
 
     def __init__(self, lattice, nx, ny, tau, wall_b=(0.0, 0.0, 1.0),
                  wall_t=(0.0, 0.0, 1.0), rho0=None, u0=None, T0=None,
-                 accommodation=(1.0, 1.0), viscosity_exp=None):
+                 accommodation=(1.0, 1.0), viscosity_exp=None, force=None):
         self.alpha = (float(accommodation[0]), float(accommodation[1]))
         self.law = None if viscosity_exp is None else np.array([float(viscosity_exp)])
+        self.force = None if force is None else np.array([float(v) for v in force])
         self.lat = _lat.by_name(lattice) if isinstance(lattice, str) else lattice
         self._la = _LatArgs(self.lat)
         self.nx, self.ny, self.tau = int(nx), int(ny), float(tau)
@@ -149,7 +151,8 @@ class OracleCase:
         rc = _load().orc_run(*self._la.args(), self.nx, self.ny, self.tau,
                              _p(self.wall_b), _p(self.wall_t), self.alpha[0], self.alpha[1],
                              _p(self.f), int(nsteps), _p(flux) if record_flux else None,
-                             None if self.law is None else _p(self.law))
+                             None if self.law is None else _p(self.law),
+                             None if self.force is None else _p(self.force))
         if rc != 0:
             raise RuntimeError("oracle run failed (%d)" % rc)
         self.t += int(nsteps)
@@ -158,7 +161,8 @@ class OracleCase:
     def moments(self) -> dict:
         out = np.empty((len(FIELDS), self.ny, self.nx))
         _load().orc_moments(*self._la.args(), self.nx, self.ny, self.tau,
-                            _p(self.f), _p(out), None if self.law is None else _p(self.law))
+                            _p(self.f), _p(out), None if self.law is None else _p(self.law),
+                            None if self.force is None else _p(self.force))
         return {k: out[i] for i, k in enumerate(FIELDS)}
 
     def mass(self) -> float:
