@@ -217,6 +217,21 @@ int lbm_set_accommodation(lbm_ctx *ctx, double alpha_bottom, double alpha_top);
  * the last step, so the law governs the collisions of later steps. */
 int lbm_set_viscosity_law(lbm_ctx *ctx, int enable, double exponent);
 
+/* Body force: a constant acceleration (ax, ay, az) of every node, in
+ * velocity units (those of the wall velocities) gained per time step; for a
+ * force-driven (Poiseuille) channel take ax != 0 with walls at rest.  Not in
+ * the paper: its Boltzmann force term -a . grad_c f is projected on the
+ * Hermite polynomials up to the equilibrium's order, which gives
+ * F = a . d f^eq / du, and the change of variable of Sec. II applied to the
+ * collision and this term gives
+ *   f*~ = f~ - (f~ - f^eq)/(tau + 1/2) + tau/(tau + 1/2) F,
+ * f^eq and F taken at the moments of f: u = u[f~] + a/2 and
+ * T = T[f~] + |a|^2/(4D) (these are the reported u and T).  (0, 0, 0), the
+ * default, is the force-free scheme.  Requires finite |a_i| <= 1 and
+ * az = 0 on the 2-D sets, else LBM_EINVAL and nothing changes.  Host-only;
+ * governs the collisions of later steps. */
+int lbm_set_body_force(lbm_ctx *ctx, double ax, double ay, double az);
+
 /* Kernel timing with HIP events (profiling aid).  While enabled, lbm_step
  * brackets every launch of the wall-sum kernel and of the fused update kernel
  * with events on the context stream and accumulates their durations; the

@@ -17,9 +17,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = [os.path.join(CSRC, "lbm_set_%s_%s.hip" % (s, p))
-           for s in ("d3q121", "d2q17", "d2q16") for p in ("fp64", "fp32", "bf16", "fp16", "fp32s")] + \
-    [os.path.join(CSRC, "lbm_batch_%s.hip" % p) for p in ("fp64", "fp32", "bf16", "fp16", "fp32s")] + \
+SOURCES = [os.path.join(CSRC, "lbm_set_%s_%s%s.hip" % (s, p, f))
+           for s in ("d3q121", "d2q17", "d2q16") for p in ("fp64", "fp32", "bf16", "fp16", "fp32s")
+           for f in ("", "_force")] + \
+    [os.path.join(CSRC, "lbm_batch_%s%s.hip" % (p, f))
+     for p in ("fp64", "fp32", "bf16", "fp16", "fp32s") for f in ("", "_force")] + \
     [os.path.join(CSRC, "lbm_dispatch.hip"), os.path.join(CSRC, "lbm_api.cpp")]
 
 HIPCC_FLAGS = [

@@ -24,6 +24,7 @@ struct lbm_ctx {
   double alpha_b, alpha_t;  // accommodation (1: the paper's diffuse wall)
   int law;                  // 1: local tau from the viscosity law
   double vexp;              // its exponent w
+  double acc[3];            // body force (acceleration per step); 0: none
   hipStream_t stream;
   bool owns;
   char* base;
@@ -126,6 +127,10 @@ StepArgs make_args(lbm_ctx* c, const void* fin, void* fout, double* mom) {
   a.tau = c->tau;
   a.vexp = c->vexp;
   a.law = c->law;
+  a.ax = c->acc[0];
+  a.ay = c->acc[1];
+  a.az = c->acc[2];
+  a.force = (c->acc[0] != 0.0 || c->acc[1] != 0.0 || c->acc[2] != 0.0) ? 1 : 0;
   a.step = uint32_t(c->steps);
   a.seed = 0x2545f491u;
   return a;
@@ -545,12 +550,18 @@ int lbm_batch_run(lbm_ctx* const* ctxs, int n_ctx, const int64_t* budgets, int64
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return LBM_EINVAL;  // one context twice would race
   }
-  // group the cases by storage format: one launch per format present
+  // group the cases by storage format and force variant: one launch per
+  // group present (group = format + kPrecCount * has_force)
+  constexpr int kGroups = 2 * kPrecCount;
   std::vector<CaseDesc> desc(n_ctx);
   std::vector<int> pos(n_ctx), fmt(n_ctx);
-  int start[kPrecCount + 1] = {};
-  for (int i = 0; i < n_ctx; ++i) fmt[i] = ctxs[i]->prec;
-  if (!plan_groups(fmt.data(), n_ctx, kPrecCount, start, pos.data())) return LBM_EINVAL;
+  int start[kGroups + 1] = {};
+  for (int i = 0; i < n_ctx; ++i) {
+    const lbm_ctx* c = ctxs[i];
+    const bool force = c->acc[0] != 0.0 || c->acc[1] != 0.0 || c->acc[2] != 0.0;
+    fmt[i] = c->prec + (force ? kPrecCount : 0);
+  }
+  if (!plan_groups(fmt.data(), n_ctx, kGroups, start, pos.data())) return LBM_EINVAL;
   for (int i = 0; i < n_ctx; ++i) {
     lbm_ctx* c = ctxs[i];
     CaseDesc& d = desc[pos[i]];
@@ -584,11 +595,12 @@ int lbm_batch_run(lbm_ctx* const* ctxs, int n_ctx, const int64_t* budgets, int64
   if (!hip_ok(hipMemcpyAsync(ddesc, desc.data(), sizeof(CaseDesc) * size_t(n_ctx),
                              hipMemcpyHostToDevice, stream)))
     return LBM_EDEVICE;
-  for (int p = 0; p < kPrecCount; ++p) {
+  for (int p = 0; p < kGroups; ++p) {
     const int cnt = start[p + 1] - start[p];
     if (cnt == 0) continue;
     if (cnt < 0 || start[p] + cnt > n_ctx) return LBM_EINVAL;  // grouping is inconsistent
-    if (!hip_ok(launch_batch(p, ddesc + start[p], cnt, dout + start[p], stream)))
+    if (!hip_ok(launch_batch(p % kPrecCount, p >= kPrecCount, ddesc + start[p], cnt,
+                             dout + start[p], stream)))
       return LBM_EDEVICE;
   }
   if (!hip_ok(hipMemcpyAsync(out.data(), dout, sizeof(CaseOut) * out.size(),
@@ -642,6 +654,16 @@ int lbm_set_viscosity_law(lbm_ctx* c, int enable, double exponent) {
     c->law = 0;
     c->vexp = 0.0;
   }
+  return LBM_OK;
+}
+
+int lbm_set_body_force(lbm_ctx* c, double ax, double ay, double az) {
+  if (!c) return LBM_EINVAL;
+  const double v[3] = {ax, ay, az};
+  for (double x : v)
+    if (!std::isfinite(x) || std::fabs(x) > 1.0) return LBM_EINVAL;
+  if (c->D == 2 && az != 0.0) return LBM_EINVAL;
+  for (int i = 0; i < 3; ++i) c->acc[i] = v[i];
   return LBM_OK;
 }
 

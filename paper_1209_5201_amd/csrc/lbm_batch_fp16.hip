@@ -2,5 +2,5 @@
 #define LBM_DEFINE_BATCH
 #include "lbm_device.hpp"
 
-template hipError_t lbm::dev::batch_launch<lbm::dev::CFP16>(const lbm::CaseDesc*, int,
+template hipError_t lbm::dev::batch_launch<lbm::dev::CFP16, false>(const lbm::CaseDesc*, int,
                                                        lbm::CaseOut*, hipStream_t);

@@ -3,5 +3,5 @@
 #define LBM_DEFINE_BATCH
 #include "lbm_device.hpp"
 
-template hipError_t lbm::dev::batch_launch<lbm::dev::CF32S>(const lbm::CaseDesc*, int,
+template hipError_t lbm::dev::batch_launch<lbm::dev::CF32S, false>(const lbm::CaseDesc*, int,
                                                         lbm::CaseOut*, hipStream_t);

@@ -1,0 +1,7 @@
+// Batched persistent small-case kernel, FP32 storage with FP64 arithmetic, body-force variant.
+// (all velocity sets).
+#define LBM_DEFINE_BATCH
+#include "lbm_device.hpp"
+
+template hipError_t lbm::dev::batch_launch<lbm::dev::CF32S, true>(const lbm::CaseDesc*, int,
+                                                        lbm::CaseOut*, hipStream_t);

@@ -226,6 +226,8 @@ __device__ __forceinline__ Rsrc plane_set(const void* p, long long plane) {
 template <class L, class R>
 struct EqCoef {
   R k0a, k0b, k0c, k1a, k1b, k2a, k2b, k3, k4;
+  // d (f^eq_q / w_q) / d(u.u) at fixed x = c.u, theta: d0a + cc d0b + x (d1 + x d2)
+  R d0a, d0b, d1, d2;
 
   __host__ __device__ static EqCoef make(R rho, R drho, R uu, R th) {
     constexpr R D = R(L::D);
@@ -241,6 +243,10 @@ struct EqCoef {
       c.k2b = rho * (R(0.25) * th);
       c.k3 = rho * R(1.0 / 6.0);
       c.k4 = rho * R(1.0 / 24.0);
+      c.d0a = rho * (-R(0.5) + R(0.25) * uu + R(0.25) * (D + 2) * th);
+      c.d0b = rho * (-R(0.25) * th);
+      c.d1 = rho * -R(0.5);
+      c.d2 = rho * -R(0.25);
     } else if constexpr (L::EQ == 3) {
       c.k0a = drho + rho * (-R(0.5) * uu - R(0.5) * D * th);
       c.k0b = rho * (R(0.5) * th);
@@ -248,13 +254,40 @@ struct EqCoef {
       c.k1b = rho * (R(0.5) * th);
       c.k2a = rho * R(0.5);
       c.k3 = rho * R(1.0 / 6.0);
+      c.d0a = rho * -R(0.5);
+      c.d1 = rho * -R(0.5);
     } else {
       c.k0a = drho + rho * (-R(0.5) * uu - R(0.5) * D * th);
       c.k0b = rho * (R(0.5) * th);
       c.k1a = rho;
       c.k2a = rho * R(0.5);
+      c.d0a = rho * -R(0.5);
     }
     return c;
+  }
+
+  // Body-force term (f^eq's directional derivative in u at fixed rho, T)
+  // over w_q: F_q / w_q = (a.c) dP/dx + 2 (a.u) dP/d(u.u), P = f^eq_q / w_q.
+  template <int EE>
+  __host__ __device__ R force(R x, R ac, R au) const {
+    constexpr R cc = R(L::R * L::R * EE);
+    R K1, K2;
+    if constexpr (L::THERMAL) {
+      K1 = k1a + cc * k1b;
+      K2 = k2a + cc * k2b;
+    } else {
+      K1 = k1a;
+      K2 = k2a;
+    }
+    R px;
+    if constexpr (L::EQ >= 4) px = K1 + x * (R(2) * K2 + x * (R(3) * k3 + x * (R(4) * k4)));
+    else if constexpr (L::EQ == 3) px = K1 + x * (R(2) * K2 + x * (R(3) * k3));
+    else px = K1 + x * (R(2) * K2);
+    R puu;
+    if constexpr (L::EQ >= 4) puu = d0a + cc * d0b + x * (d1 + x * d2);
+    else if constexpr (L::EQ == 3) puu = d0a + x * d1;
+    else puu = d0a;
+    return ac * px + R(2) * au * puu;
   }
 
   // (f^eq_q - w_q) / w_q at x = c_q.u, for |e_q|^2 = EE.
@@ -330,10 +363,25 @@ __device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
 //   moments (fourth-order f^eq on D2Q17 and D3Q121).
 // D2Q16's second-order f^eq does not: its heat flux sums f - w and adds
 //   sum_q w_q |C|^2 C_i = -u_i (D + 2 + |u|^2).
-template <class L, class R, bool MOM = false>
+// FORCE: a body force a (not in the paper).  Its Hermite-projected term is
+// F = a . d f^eq / du; the trapezoidal change of variable of Sec. II applied
+// to collision + force gives g* = g + omega (f^eq - w - g) + tau/(tau+1/2) F
+// with f^eq and F at the moments of f: u = u[f~] + a/2, T = T[f~] + a^2/(4D).
+template <class L, class R, bool MOM = false, bool FORCE = false>
 __device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* mom = nullptr,
                                       long long nodes = 0, long long n = 0) {
-  const Macro<R> m = macro<L, R>(g);
+  Macro<R> m = macro<L, R>(g);
+  R fax = 0, fay = 0, faz = 0;
+  if constexpr (FORCE) {
+    // moments of f from those of f~: u + a/2, T + a^2/(4D)
+    fax = R(a.ax);
+    fay = R(a.ay);
+    faz = R(a.az);
+    m.ux += R(0.5) * fax;
+    m.uy += R(0.5) * fay;
+    m.uz += R(0.5) * faz;
+    if constexpr (L::THERMAL) m.th += (fax * fax + fay * fay + faz * faz) * R(0.25 / L::D);
+  }
   const R uu = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
   const auto k = EqCoef<L, R>::make(m.rho, m.drho, uu, m.th);
   constexpr R r = R(L::R);
@@ -347,17 +395,28 @@ __device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* m
       kf = tn * omega;
     }
   }
+  const R au = fax * m.ux + fay * m.uy + faz * m.uz;
   R sxy = 0, qx = 0, qy = 0, qz = 0;
   auto body = [&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
+    constexpr int EE = ex * ex + ey * ey + ez * ez;
     R x = R(0);
     x = add_scaled<ex>(x, sx);
     x = add_scaled<ey>(x, sy);
     x = add_scaled<ez>(x, sz);
-    const R geq = R(L::W[q]) * k.template poly<ex * ex + ey * ey + ez * ez>(x);
+    const R geq = R(L::W[q]) * k.template poly<EE>(x);
+    R F = R(0);
+    if constexpr (FORCE) {
+      R ac = R(0);
+      ac = add_scaled<ex>(ac, fax);
+      ac = add_scaled<ey>(ac, fay);
+      ac = add_scaled<ez>(ac, faz);
+      F = R(L::W[q]) * k.template force<EE>(x, r * ac, au);
+    }
     if constexpr (MOM) {
-      const R neq = g[q] - geq;  // f~ - f^eq
+      // f~ - f^eq (+ F/2 under a force: f - f^eq = tau/(tau+1/2) (f~ + F/2 - f^eq))
+      const R neq = FORCE ? g[q] - geq + R(0.5) * F : g[q] - geq;
       const R Cx = R(L::R * ex) - m.ux, Cy = R(L::R * ey) - m.uy, Cz = R(L::R * ez) - m.uz;
       const R C2 = Cx * Cx + Cy * Cy + Cz * Cz;
       sxy += neq * Cx * Cy;
@@ -366,7 +425,10 @@ __device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* m
       qy += fq * C2 * Cy;
       qz += fq * C2 * Cz;
     }
-    g[q] = g[q] + omega * (geq - g[q]);
+    if constexpr (FORCE)
+      g[q] = g[q] + omega * (geq - g[q]) + kf * F;
+    else
+      g[q] = g[q] + omega * (geq - g[q]);
   };
   static_for<0, L::Q>(body);
   if constexpr (MOM) {
@@ -636,7 +698,7 @@ __device__ __forceinline__ double ghost_column_deviation(const StepArgs& a, int 
 
 // Any grid shape: one thread per node on a linear node index; the ghost
 // ratios come from wall_kernel, launched before.
-template <class L, class C, bool MOM>
+template <class L, class C, bool MOM, bool FORCE>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
   using R = typename C::R;
   constexpr int NS = max_ex<L>();
@@ -651,7 +713,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
   pull<L, C>(f, a, y, xw,
              [&](int wall, int ex) { return a.ratio[wall * a.nx + xw[ex + NS]]; });
   wall_specular<L, C>(f, a, y, xw);
-  relax<L, R, MOM>(f, a, a.mom, nodes, n);
+  relax<L, R, MOM, FORCE>(f, a, a.mom, nodes, n);
   store<L, C>(f, a, uint32_t(n));
 }
 
@@ -661,7 +723,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
 // N rows next to a wall first compute the pooled ghost-column ratios of the
 // kBlock + 2 NS columns their pulls can reach into LDS (fusing the wall sums
 // into the update: no separate launch, no global round trip).
-template <class L, class C, bool MOM>
+template <class L, class C, bool MOM, bool FORCE>
 __global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
   using R = typename C::R;
   constexpr int NS = max_ex<L>();
@@ -690,14 +752,14 @@ __global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
   if (bottom || top) wall_specular<L, C>(f, a, y, xw);
   const long long nodes = (long long)a.nx * a.ny;
   const uint32_t n = uint32_t(y) * uint32_t(a.nx) + uint32_t(x);
-  relax<L, R, MOM>(f, a, a.mom, nodes, n);
+  relax<L, R, MOM, FORCE>(f, a, a.mom, nodes, n);
   store<L, C>(f, a, n);
 }
 
 // f~(0) = f^eq(rho0, u0, T0); writes the output fields of f~(0) and stores
 // f*(0) = relaxed f~(0), the state every later step pulls from (as
 // deviations from the rest weights).
-template <class L, class C>
+template <class L, class C, bool FORCE>
 __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double* fields) {
   using R = typename C::R;
   const long long nodes = (long long)a.nx * a.ny;
@@ -721,7 +783,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double* 
     f[q] = R(L::W[q] * k.template poly<ex * ex + ey * ey + ez * ez>(x));  // f^eq - w
   };
   static_for<0, L::Q>(body);
-  relax<L, R, true>(f, a, a.mom, nodes, n);
+  relax<L, R, true, FORCE>(f, a, a.mom, nodes, n);
   store<L, C>(f, a, uint32_t(n));
 }
 
@@ -770,7 +832,7 @@ __device__ __forceinline__ void residual_terms(const double* mom, double* snap, 
 // kernel and the case stops once the residual is below its tolerance.  A
 // case's arithmetic and stopping point depend only on its own data, so its
 // result is the same alone and in any mix, and whatever its step budget.
-template <class L, class C>
+template <class L, class C, bool FORCE>
 __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, double* ratio_s,
                                          double (*red)[kBatchBlock]) {
   using R = typename C::R;
@@ -810,9 +872,9 @@ __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, doubl
                    [&](int wall, int ex) { return ratio_s[wall * a.nx + xw[ex + NS]]; });
         wall_specular<L, C>(f, a, y, xw);
         if (last)
-          relax<L, R, true>(f, a, a.mom, nodes, n);
+          relax<L, R, true, FORCE>(f, a, a.mom, nodes, n);
         else
-          relax<L, R>(f, a);
+          relax<L, R, false, FORCE>(f, a);
         store<L, C, kStoreCached>(f, a, uint32_t(n));
       }
       __syncthreads();
@@ -846,16 +908,16 @@ __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, doubl
   }
 }
 
-template <class C>
+template <class C, bool FORCE>
 __global__ __launch_bounds__(kBatchBlock) void batch_kernel(const CaseDesc* __restrict__ cases,
                                                             CaseOut* out) {
   __shared__ double ratio_s[2 * kBatchMaxNx];
   __shared__ double red[4][kBatchBlock];
   const CaseDesc& cd = cases[blockIdx.x];
   switch (cd.lattice) {
-    case 0: run_case<D2Q16, C>(cd, out, ratio_s, red); break;
-    case 1: run_case<D2Q17, C>(cd, out, ratio_s, red); break;
-    case 2: run_case<D3Q121, C>(cd, out, ratio_s, red); break;
+    case 0: run_case<D2Q16, C, FORCE>(cd, out, ratio_s, red); break;
+    case 1: run_case<D2Q17, C, FORCE>(cd, out, ratio_s, red); break;
+    case 2: run_case<D3Q121, C, FORCE>(cd, out, ratio_s, red); break;
   }
 }
 
@@ -868,10 +930,11 @@ inline unsigned grid_for(long long threads) {
   return unsigned((threads + kBlock - 1) / kBlock);
 }
 
-// Launchers of one (velocity set, storage format) pair, instantiated in its
-// own translation unit (lbm_set_*.hip) so that the pairs compile in
-// parallel.
-template <class L, class C>
+// Launchers of one (velocity set, storage format, body force or not)
+// triple, instantiated in its own translation unit (lbm_set_*.hip) so that
+// they compile in parallel.  The force is a compile-time variant: the
+// force-free kernels carry none of its code or registers.
+template <class L, class C, bool FORCE>
 struct SetOps {
   static hipError_t wall(const StepArgs& a, hipStream_t s);
   static hipError_t step(const StepArgs& a, bool moments, hipStream_t s);
@@ -880,79 +943,109 @@ struct SetOps {
 };
 
 #ifdef LBM_DEFINE_SET_OPS
-template <class L, class C>
-hipError_t SetOps<L, C>::wall(const StepArgs& a, hipStream_t s) {
+template <class L, class C, bool FORCE>
+hipError_t SetOps<L, C, FORCE>::wall(const StepArgs& a, hipStream_t s) {
   clear_stale_error();
   hipLaunchKernelGGL((wall_kernel<L, C>), dim3(grid_for(2LL * a.nx * 64)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-template <class L, class C>
-hipError_t SetOps<L, C>::step(const StepArgs& a, bool moments, hipStream_t s) {
+template <class L, class C, bool FORCE>
+hipError_t SetOps<L, C, FORCE>::step(const StepArgs& a, bool moments, hipStream_t s) {
   const dim3 grid(grid_for((long long)a.nx * a.ny));
   clear_stale_error();
   if (moments)
-    hipLaunchKernelGGL((step_kernel<L, C, true>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((step_kernel<L, C, true, FORCE>), grid, dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((step_kernel<L, C, false>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((step_kernel<L, C, false, FORCE>), grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-template <class L, class C>
-hipError_t SetOps<L, C>::step_rows(const StepArgs& a, bool moments, hipStream_t s) {
+template <class L, class C, bool FORCE>
+hipError_t SetOps<L, C, FORCE>::step_rows(const StepArgs& a, bool moments, hipStream_t s) {
   const dim3 grid(unsigned(a.nx / kBlock) * unsigned(a.ny));
   clear_stale_error();
   if (moments)
-    hipLaunchKernelGGL((step_rows_kernel<L, C, true>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((step_rows_kernel<L, C, true, FORCE>), grid, dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((step_rows_kernel<L, C, false>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((step_rows_kernel<L, C, false, FORCE>), grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-template <class L, class C>
-hipError_t SetOps<L, C>::init(const StepArgs& a, const double* fields, hipStream_t s) {
+template <class L, class C, bool FORCE>
+hipError_t SetOps<L, C, FORCE>::init(const StepArgs& a, const double* fields, hipStream_t s) {
   clear_stale_error();
-  hipLaunchKernelGGL((init_kernel<L, C>), dim3(grid_for((long long)a.nx * a.ny)), dim3(kBlock),
-                     0, s, a, fields);
+  hipLaunchKernelGGL((init_kernel<L, C, FORCE>), dim3(grid_for((long long)a.nx * a.ny)),
+                     dim3(kBlock), 0, s, a, fields);
   return hipGetLastError();
 }
 #endif
 
 // Batched persistent launch of one storage format (lbm_batch_*.hip).
-template <class C>
+template <class C, bool FORCE>
 hipError_t batch_launch(const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s);
 
 #ifdef LBM_DEFINE_BATCH
-template <class C>
+template <class C, bool FORCE>
 hipError_t batch_launch(const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s) {
   clear_stale_error();
-  hipLaunchKernelGGL((batch_kernel<C>), dim3(unsigned(ncase)), dim3(kBatchBlock), 0, s, cases,
-                     out);
+  hipLaunchKernelGGL((batch_kernel<C, FORCE>), dim3(unsigned(ncase)), dim3(kBatchBlock), 0, s,
+                     cases, out);
   return hipGetLastError();
 }
 #endif
 
-extern template hipError_t batch_launch<CF64>(const CaseDesc*, int, CaseOut*, hipStream_t);
-extern template hipError_t batch_launch<CF32>(const CaseDesc*, int, CaseOut*, hipStream_t);
-extern template hipError_t batch_launch<CBF16>(const CaseDesc*, int, CaseOut*, hipStream_t);
-extern template hipError_t batch_launch<CFP16>(const CaseDesc*, int, CaseOut*, hipStream_t);
-extern template hipError_t batch_launch<CF32S>(const CaseDesc*, int, CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF64, false>(const CaseDesc*, int, CaseOut*,
+                                                       hipStream_t);
+extern template hipError_t batch_launch<CF64, true>(const CaseDesc*, int, CaseOut*,
+                                                       hipStream_t);
+extern template hipError_t batch_launch<CF32, false>(const CaseDesc*, int, CaseOut*,
+                                                       hipStream_t);
+extern template hipError_t batch_launch<CF32, true>(const CaseDesc*, int, CaseOut*,
+                                                       hipStream_t);
+extern template hipError_t batch_launch<CBF16, false>(const CaseDesc*, int, CaseOut*,
+                                                       hipStream_t);
+extern template hipError_t batch_launch<CBF16, true>(const CaseDesc*, int, CaseOut*,
+                                                       hipStream_t);
+extern template hipError_t batch_launch<CFP16, false>(const CaseDesc*, int, CaseOut*,
+                                                       hipStream_t);
+extern template hipError_t batch_launch<CFP16, true>(const CaseDesc*, int, CaseOut*,
+                                                       hipStream_t);
+extern template hipError_t batch_launch<CF32S, false>(const CaseDesc*, int, CaseOut*,
+                                                       hipStream_t);
+extern template hipError_t batch_launch<CF32S, true>(const CaseDesc*, int, CaseOut*,
+                                                       hipStream_t);
 
-extern template struct SetOps<D2Q16, CF64>;
-extern template struct SetOps<D2Q16, CF32>;
-extern template struct SetOps<D2Q16, CBF16>;
-extern template struct SetOps<D2Q16, CFP16>;
-extern template struct SetOps<D2Q16, CF32S>;
-extern template struct SetOps<D2Q17, CF64>;
-extern template struct SetOps<D2Q17, CF32>;
-extern template struct SetOps<D2Q17, CBF16>;
-extern template struct SetOps<D2Q17, CFP16>;
-extern template struct SetOps<D2Q17, CF32S>;
-extern template struct SetOps<D3Q121, CF64>;
-extern template struct SetOps<D3Q121, CF32>;
-extern template struct SetOps<D3Q121, CBF16>;
-extern template struct SetOps<D3Q121, CFP16>;
-extern template struct SetOps<D3Q121, CF32S>;
+extern template struct SetOps<D2Q16, CF64, false>;
+extern template struct SetOps<D2Q16, CF64, true>;
+extern template struct SetOps<D2Q16, CF32, false>;
+extern template struct SetOps<D2Q16, CF32, true>;
+extern template struct SetOps<D2Q16, CBF16, false>;
+extern template struct SetOps<D2Q16, CBF16, true>;
+extern template struct SetOps<D2Q16, CFP16, false>;
+extern template struct SetOps<D2Q16, CFP16, true>;
+extern template struct SetOps<D2Q16, CF32S, false>;
+extern template struct SetOps<D2Q16, CF32S, true>;
+extern template struct SetOps<D2Q17, CF64, false>;
+extern template struct SetOps<D2Q17, CF64, true>;
+extern template struct SetOps<D2Q17, CF32, false>;
+extern template struct SetOps<D2Q17, CF32, true>;
+extern template struct SetOps<D2Q17, CBF16, false>;
+extern template struct SetOps<D2Q17, CBF16, true>;
+extern template struct SetOps<D2Q17, CFP16, false>;
+extern template struct SetOps<D2Q17, CFP16, true>;
+extern template struct SetOps<D2Q17, CF32S, false>;
+extern template struct SetOps<D2Q17, CF32S, true>;
+extern template struct SetOps<D3Q121, CF64, false>;
+extern template struct SetOps<D3Q121, CF64, true>;
+extern template struct SetOps<D3Q121, CF32, false>;
+extern template struct SetOps<D3Q121, CF32, true>;
+extern template struct SetOps<D3Q121, CBF16, false>;
+extern template struct SetOps<D3Q121, CBF16, true>;
+extern template struct SetOps<D3Q121, CFP16, false>;
+extern template struct SetOps<D3Q121, CFP16, true>;
+extern template struct SetOps<D3Q121, CF32S, false>;
+extern template struct SetOps<D3Q121, CF32S, true>;
 
 }  // namespace dev
 }  // namespace lbm

@@ -34,16 +34,28 @@ __global__ __launch_bounds__(kBlock) void reduce_final(ReduceArgs r) {
 
 namespace {
 
-template <class L, class F>
-hipError_t by_prec(int prec, F&& fn) {
+template <class L, bool FORCE, class F>
+hipError_t by_prec_f(int prec, F&& fn) {
   switch (prec) {
-    case kFP64: return fn(dev::SetOps<L, dev::CF64>{});
-    case kFP32: return fn(dev::SetOps<L, dev::CF32>{});
-    case kBF16: return fn(dev::SetOps<L, dev::CBF16>{});
-    case kFP16: return fn(dev::SetOps<L, dev::CFP16>{});
-    case kFP32S: return fn(dev::SetOps<L, dev::CF32S>{});
+    case kFP64: return fn(dev::SetOps<L, dev::CF64, FORCE>{});
+    case kFP32: return fn(dev::SetOps<L, dev::CF32, FORCE>{});
+    case kBF16: return fn(dev::SetOps<L, dev::CBF16, FORCE>{});
+    case kFP16: return fn(dev::SetOps<L, dev::CFP16, FORCE>{});
+    case kFP32S: return fn(dev::SetOps<L, dev::CF32S, FORCE>{});
   }
   return hipErrorInvalidValue;
+}
+
+// the body-force variant when the step's arguments carry a force
+template <class L, class F>
+hipError_t by_prec(int prec, const StepArgs& a, F&& fn) {
+  return a.force ? by_prec_f<L, true>(prec, fn) : by_prec_f<L, false>(prec, fn);
+}
+
+template <class C>
+hipError_t batch_of(bool force, const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s) {
+  return force ? dev::batch_launch<C, true>(cases, ncase, out, s)
+               : dev::batch_launch<C, false>(cases, ncase, out, s);
 }
 
 template <class F>
@@ -60,13 +72,13 @@ hipError_t by_set(int lattice, F&& fn) {
 
 hipError_t launch_wall(int lattice, int prec, const StepArgs& a, hipStream_t s) {
   return by_set(lattice, [&](auto lat) {
-    return by_prec<decltype(lat)>(prec, [&](auto ops) { return decltype(ops)::wall(a, s); });
+    return by_prec<decltype(lat)>(prec, a, [&](auto ops) { return decltype(ops)::wall(a, s); });
   });
 }
 
 hipError_t launch_step(int lattice, int prec, const StepArgs& a, bool moments, hipStream_t s) {
   return by_set(lattice, [&](auto lat) {
-    return by_prec<decltype(lat)>(prec,
+    return by_prec<decltype(lat)>(prec, a,
                                   [&](auto ops) { return decltype(ops)::step(a, moments, s); });
   });
 }
@@ -75,14 +87,14 @@ hipError_t launch_step_rows(int lattice, int prec, const StepArgs& a, bool momen
                             hipStream_t s) {
   return by_set(lattice, [&](auto lat) {
     return by_prec<decltype(lat)>(
-        prec, [&](auto ops) { return decltype(ops)::step_rows(a, moments, s); });
+        prec, a, [&](auto ops) { return decltype(ops)::step_rows(a, moments, s); });
   });
 }
 
 hipError_t launch_init(int lattice, int prec, const StepArgs& a, const double* fields,
                        hipStream_t s) {
   return by_set(lattice, [&](auto lat) {
-    return by_prec<decltype(lat)>(prec,
+    return by_prec<decltype(lat)>(prec, a,
                                   [&](auto ops) { return decltype(ops)::init(a, fields, s); });
   });
 }
@@ -96,15 +108,15 @@ hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch(int prec, const CaseDesc* cases, int ncase, CaseOut* out,
+hipError_t launch_batch(int prec, bool force, const CaseDesc* cases, int ncase, CaseOut* out,
                         hipStream_t s) {
   if (ncase <= 0 || !cases || !out) return hipErrorInvalidValue;  // one workgroup per case
   switch (prec) {
-    case kFP64: return dev::batch_launch<dev::CF64>(cases, ncase, out, s);
-    case kFP32: return dev::batch_launch<dev::CF32>(cases, ncase, out, s);
-    case kBF16: return dev::batch_launch<dev::CBF16>(cases, ncase, out, s);
-    case kFP16: return dev::batch_launch<dev::CFP16>(cases, ncase, out, s);
-    case kFP32S: return dev::batch_launch<dev::CF32S>(cases, ncase, out, s);
+    case kFP64: return batch_of<dev::CF64>(force, cases, ncase, out, s);
+    case kFP32: return batch_of<dev::CF32>(force, cases, ncase, out, s);
+    case kBF16: return batch_of<dev::CBF16>(force, cases, ncase, out, s);
+    case kFP16: return batch_of<dev::CFP16>(force, cases, ncase, out, s);
+    case kFP32S: return batch_of<dev::CF32S>(force, cases, ncase, out, s);
   }
   return hipErrorInvalidValue;
 }

@@ -46,6 +46,8 @@ struct StepArgs {
   double tau;           // relaxation time at rho = T = 1
   double vexp;          // viscosity exponent w of the local law (law != 0)
   int law;              // 0: constant tau; 1: tau T^(w-1) / rho per node
+  int force;            // 1: body force (ax, ay, az) acts
+  double ax, ay, az;    // acceleration per time step (velocity units)
   uint32_t step;        // index of the step being produced (rounding counter)
   uint32_t seed;        // per-context rounding seed
 };
@@ -95,12 +97,14 @@ hipError_t launch_step_rows(int lattice, int prec, const StepArgs& a, bool momen
 hipError_t launch_init(int lattice, int prec, const StepArgs& a,
                        const double* fields, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s);
-// One workgroup per case advances every case of one storage precision in
+// One workgroup per case advances every case of one storage precision (and
+// one force variant: all cases with or all without a body force) in
 // windows of cases[i].window steps, up to cases[i].budget steps, stopping a
 // case after the first window whose residual is below cases[i].tol; writes
 // each case's fields after its last window, its mass / residual sums into
 // its result block, and out[i].
-hipError_t launch_batch(int prec, const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s);
+hipError_t launch_batch(int prec, bool force, const CaseDesc* cases, int ncase, CaseOut* out,
+                        hipStream_t s);
 
 // Host helpers (no device work).
 // g^eq_q(u, T) of every velocity with unit density (wall Maxwellians).

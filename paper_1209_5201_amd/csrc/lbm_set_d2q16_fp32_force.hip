@@ -1,0 +1,5 @@
+// Kernels of the D2Q16 velocity set with FP32 storage, body-force variant.
+#define LBM_DEFINE_SET_OPS
+#include "lbm_device.hpp"
+
+template struct lbm::dev::SetOps<lbm::D2Q16, lbm::dev::CF32, true>;

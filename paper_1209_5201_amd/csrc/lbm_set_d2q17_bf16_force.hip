@@ -1,0 +1,5 @@
+// Kernels of the D2Q17 velocity set with BF16 deviation storage, body-force variant.
+#define LBM_DEFINE_SET_OPS
+#include "lbm_device.hpp"
+
+template struct lbm::dev::SetOps<lbm::D2Q17, lbm::dev::CBF16, true>;

@@ -2,4 +2,4 @@
 #define LBM_DEFINE_SET_OPS
 #include "lbm_device.hpp"
 
-template struct lbm::dev::SetOps<lbm::D2Q17, lbm::dev::CF32S>;
+template struct lbm::dev::SetOps<lbm::D2Q17, lbm::dev::CF32S, false>;

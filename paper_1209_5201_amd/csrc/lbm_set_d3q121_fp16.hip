@@ -2,4 +2,4 @@
 #define LBM_DEFINE_SET_OPS
 #include "lbm_device.hpp"
 
-template struct lbm::dev::SetOps<lbm::D3Q121, lbm::dev::CFP16>;
+template struct lbm::dev::SetOps<lbm::D3Q121, lbm::dev::CFP16, false>;

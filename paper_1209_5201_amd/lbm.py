@@ -101,6 +101,8 @@ def _load():
                                          _ip]),
         "lbm_set_accommodation": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
         "lbm_set_viscosity_law": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double]),
+        "lbm_set_body_force": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double]),
         "lbm_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
         "lbm_kernel_time": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp,
                                            ctypes.POINTER(ctypes.c_int64)]),
@@ -122,7 +124,7 @@ def exported_symbols():
             "lbm_create_in", "lbm_init", "lbm_step", "lbm_field", "lbm_moments",
             "lbm_residual", "lbm_mass", "lbm_steps_done", "lbm_state_bytes", "lbm_save",
             "lbm_load", "lbm_batch_step", "lbm_batch_run", "lbm_set_accommodation",
-            "lbm_set_viscosity_law", "lbm_set_timing", "lbm_kernel_time", "lbm_destroy", "lbm_strerror",
+            "lbm_set_viscosity_law", "lbm_set_body_force", "lbm_set_timing", "lbm_kernel_time", "lbm_destroy", "lbm_strerror",
             "lbm_last_device_error"]
 
 
@@ -284,6 +286,11 @@ def lbm_set_viscosity_law(ctx, exponent):
            "lbm_set_viscosity_law")
 
 
+def lbm_set_body_force(ctx, ax: float, ay: float = 0.0, az: float = 0.0):
+    _check(_load().lbm_set_body_force(ctx, float(ax), float(ay), float(az)),
+           "lbm_set_body_force")
+
+
 def lbm_set_timing(ctx, enable: bool):
     _check(_load().lbm_set_timing(ctx, int(bool(enable))), "lbm_set_timing")
 
@@ -311,7 +318,7 @@ class Channel:
 
     def __init__(self, lattice, nx, ny, tau, bottom=(0.0, 0.0, 1.0), top=(0.0, 0.0, 1.0),
                  prec="fp64", device="cuda:0", kn=None, accommodation=(1.0, 1.0),
-                 viscosity_exp=None):
+                 viscosity_exp=None, force=None):
         import torch
         self.lattice = lattice if isinstance(lattice, str) else \
             {v: k for k, v in LATTICES.items()}[lattice]
@@ -331,6 +338,11 @@ class Channel:
             self.set_accommodation(*accommodation)
         if viscosity_exp is not None:
             self.set_viscosity_law(viscosity_exp)
+        if force is not None:
+            self.set_body_force(*force)
+
+    def set_body_force(self, ax, ay=0.0, az=0.0):
+        lbm_set_body_force(self.ctx, ax, ay, az)
 
     def set_viscosity_law(self, exponent):
         lbm_set_viscosity_law(self.ctx, exponent)
