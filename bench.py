@@ -128,8 +128,9 @@ def cpu_baseline(cfg, nsteps: int):
 def serving(n_requests: int, rate: float, baseline_cases: int):
     """Couette serving stream (FP32, residual 1e-8): saturated throughput
     with every request queued at t = 0, then latency at a fixed Poisson
-    arrival rate; the same first `baseline_cases` requests solved one at a
-    time in FP64 as the baseline."""
+    arrival rate; the same stream with a quarter of the requests replaced by
+    force-driven channels; the same first `baseline_cases` requests solved
+    one at a time in FP64 as the baseline."""
     from paper_1209_5201_amd import serve
     from paper_1209_5201_amd import workloads as W
     reqs = W.serving_requests(n=n_requests, seed=1, rate=rate)
@@ -137,6 +138,11 @@ def serving(n_requests: int, rate: float, baseline_cases: int):
         reqs, realtime=False)
     live = serve.Server(prec="fp32", window=100, tol=1e-8, keep_profiles=False).run(
         reqs, realtime=True)
+    mixed_reqs = W.serving_requests(n=n_requests, seed=1, rate=rate, channel_fraction=0.25)
+    mixed_sat = serve.Server(prec="fp32", window=100, tol=1e-8, keep_profiles=False).run(
+        mixed_reqs, realtime=False)
+    mixed_live = serve.Server(prec="fp32", window=100, tol=1e-8, keep_profiles=False).run(
+        mixed_reqs, realtime=True)
     base = serve.one_at_a_time(reqs[:baseline_cases], prec="fp64")
     same = serve.Server(prec="fp32", window=100, tol=1e-8, keep_profiles=False).run(
         reqs[:baseline_cases], realtime=False)
@@ -150,6 +156,13 @@ def serving(n_requests: int, rate: float, baseline_cases: int):
             "solves_per_s": r(live["solves_per_s"]),
             "p50_time_to_solution_s": r(live["p50_s"]), "p99_time_to_solution_s": r(live["p99_s"]),
             "p50_service_s": r(live["p50_service_s"]), "p99_service_s": r(live["p99_service_s"]),
+            "with_channels": {
+                "requests": n_requests, "force_driven_channels": sum("umax" in q for q in mixed_reqs),
+                "saturated_solves_per_s": r(mixed_sat["solves_per_s"]),
+                "saturated_converged": mixed_sat["converged"],
+                "solves_per_s": r(mixed_live["solves_per_s"]),
+                "p50_time_to_solution_s": r(mixed_live["p50_s"]),
+                "p99_time_to_solution_s": r(mixed_live["p99_s"])},
             "baseline": {"kind": "one at a time, FP64, same library", "requests": baseline_cases,
                          "solves_per_s": r(base["solves_per_s"]),
                          "batched_fp32_same_requests_solves_per_s": r(same["solves_per_s"])}}

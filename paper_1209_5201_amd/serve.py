@@ -1,6 +1,7 @@
 """Continuous batching of Couette / channel solves on one GPU.
 
-Requests (a channel: velocity set, ny, Kn, walls) arrive over time.  The
+Requests (a channel: velocity set, ny, Kn, walls, and optionally a body
+force for a force-driven channel) arrive over time.  The
 server admits arrived requests while it has free slots and free HBM (each
 case's footprint is lbm_required_bytes), advances every admitted case by one
 step budget in a single lbm_batch_run call (one persistent launch per
@@ -42,6 +43,15 @@ class Result:
     profiles: dict = field(default_factory=dict)   # x-averaged u_x, T, sigma_xy, q_y
 
 
+def channel_force(lattice: str, ny: int, kn: float, umax: float) -> float:
+    """Acceleration per time step that gives a force-driven channel of ny
+    rows at Knudsen number kn the no-slip Navier-Stokes peak velocity umax:
+    u_max = (a/nu)/8 in channel units, where a/nu = a_lat r ny / (sqrt(2/pi) Kn)
+    (nu = tau T with tau = sqrt(2/pi) Kn, one step dt = 1/(r ny))."""
+    r = _l.lbm_lattice_info(lattice)["r"]
+    return 8.0 * umax * math.sqrt(2.0 / math.pi) * kn / (r * ny)
+
+
 def percentile(vals, p):
     return float(np.percentile(np.asarray(vals, dtype=np.float64), p)) if len(vals) else math.nan
 
@@ -80,9 +90,12 @@ class Server:
         return self.window * windows
 
     def _open(self, req):
+        force = req.get("force")
+        if force is None and req.get("umax"):
+            force = (channel_force(req["lattice"], req["ny"], req["kn"], req["umax"]), 0.0, 0.0)
         return _l.Channel(req["lattice"], req.get("nx", 1), req["ny"], 0.0,
                           req["bottom"], req["top"], prec=self.prec, device=self.device,
-                          kn=req["kn"])
+                          kn=req["kn"], force=force)
 
     def _finish(self, slot, now, converged, residual):
         ch, req, t_admit, fp = slot

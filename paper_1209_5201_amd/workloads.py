@@ -54,12 +54,17 @@ def c3_density(nx: int = 2048, ny: int = 2048, seed: int = 0, amp: float = 1e-3,
 
 
 def serving_requests(n: int = 1024, seed: int = 1, rate: float = 100.0,
-                     ny_range=(16, 512)):
+                     ny_range=(16, 512), channel_fraction: float = 0.0):
     """Couette requests: lattice uniform over the three, Ny uniform, Kn
     log-uniform in [0.01, 0.5], U uniform in [0.01, 0.2] (walls -U / +U),
     top-wall T uniform in [1, 1.2] for the thermal lattice (1 otherwise),
-    Poisson arrivals at `rate` per second."""
+    Poisson arrivals at `rate` per second.  With channel_fraction > 0 that
+    share of the requests (drawn from a second stream, so the Couette draws
+    are unchanged) are force-driven channels instead: walls at rest at
+    T = 1, driven by the body force whose no-slip Navier-Stokes peak
+    velocity is U (key "umax"; each side derives the force itself)."""
     rng = np.random.default_rng(seed)
+    kind = np.random.default_rng([seed, 7])
     names = ("D2Q16", "D2Q17", "D3Q121")
     out = []
     t = 0.0
@@ -70,6 +75,10 @@ def serving_requests(n: int = 1024, seed: int = 1, rate: float = 100.0,
         U = float(rng.uniform(0.01, 0.2))
         Tt = float(rng.uniform(1.0, 1.2)) if lat == "D3Q121" else 1.0
         t += float(rng.exponential(1.0 / rate))
-        out.append(dict(id=i, lattice=lat, nx=1, ny=ny, kn=kn, bottom=(-U, 0.0, 1.0),
-                        top=(U, 0.0, Tt), arrival=t))
+        if channel_fraction > 0 and kind.random() < channel_fraction:
+            out.append(dict(id=i, lattice=lat, nx=1, ny=ny, kn=kn, bottom=(0.0, 0.0, 1.0),
+                            top=(0.0, 0.0, 1.0), umax=U, arrival=t))
+        else:
+            out.append(dict(id=i, lattice=lat, nx=1, ny=ny, kn=kn, bottom=(-U, 0.0, 1.0),
+                            top=(U, 0.0, Tt), arrival=t))
     return out

@@ -1,5 +1,6 @@
 """GPU tests of the batched small-case path (lbm_batch_step) and the
 continuous-batching server."""
+import math
 import sys
 
 import numpy as np
@@ -8,6 +9,7 @@ import pytest
 import paper_1209_5201_amd as lbm
 from paper_1209_5201_amd import serve
 from paper_1209_5201_amd import workloads as W
+from oracle import lattices as OL
 from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu
@@ -93,7 +95,7 @@ def test_batch_matches_oracle_fp64():
 def test_each_result_is_the_same_alone_and_in_the_mix():
     """A request served inside a mix of others returns bit-identical profiles
     and step counts to the same request served alone."""
-    reqs = W.serving_requests(n=12, seed=11, rate=1e9, ny_range=(16, 64))
+    reqs = W.serving_requests(n=12, seed=11, rate=1e9, ny_range=(16, 64), channel_fraction=0.4)
     for r in reqs:
         r["kn"] = max(r["kn"], 0.1)   # keep the test short
     say("case alone == mix", len(reqs))
@@ -126,6 +128,37 @@ def test_served_fp32_results_match_fp64_oracle():
         o = O.OracleCase(req["lattice"], 1, req["ny"],
                          O.tau_from_kn(req["lattice"], req["ny"], req["kn"]),
                          req["bottom"], req["top"])
+        o.run(res.steps)
+        want = o.moments()
+        for k in ("ux", "sxy") + (("T", "qy") if req["lattice"] == "D3Q121" else ()):
+            w = want[k][:, 0]
+            scale = np.abs(w - (1.0 if k == "T" else 0.0)).max()
+            assert np.abs(res.profiles[k] - w).max() <= 1e-5 * scale + 1e-9, (req["lattice"], k)
+
+
+def test_served_channel_requests_match_fp64_oracle():
+    """Force-driven channel requests served in FP32 beside a Couette request,
+    each against the FP64 oracle run the same number of steps with the force
+    derived from the oracle's own lattice tables."""
+    reqs = [dict(id=0, lattice="D2Q17", ny=32, kn=0.1, bottom=(0, 0, 1.0), top=(0, 0, 1.0),
+                 umax=0.08, arrival=0.0),
+            dict(id=1, lattice="D3Q121", ny=24, kn=0.2, bottom=(0, 0, 1.0), top=(0, 0, 1.0),
+                 umax=0.1, arrival=0.0),
+            dict(id=2, lattice="D2Q16", ny=40, kn=0.05, bottom=(0, 0, 1.0), top=(0, 0, 1.0),
+                 umax=0.05, arrival=0.0),
+            dict(id=3, lattice="D2Q17", ny=20, kn=0.3, bottom=(-0.1, 0, 1.0), top=(0.1, 0, 1.0),
+                 arrival=0.0)]
+    say("case served channels vs oracle")
+    out = serve.Server(prec="fp32", window=100, tol=1e-8).run(reqs, realtime=False)
+    for res, req in zip(out["results"], reqs):
+        assert res.converged
+        lat = OL.by_name(req["lattice"])
+        force = None
+        if "umax" in req:
+            a = 8 * req["umax"] * math.sqrt(2 / math.pi) * req["kn"] / (lat.r * req["ny"])
+            force = (a, 0.0, 0.0)
+        o = O.OracleCase(lat, 1, req["ny"], O.tau_from_kn(lat, req["ny"], req["kn"]),
+                         req["bottom"], req["top"], force=force)
         o.run(res.steps)
         want = o.moments()
         for k in ("ux", "sxy") + (("T", "qy") if req["lattice"] == "D3Q121" else ()):
