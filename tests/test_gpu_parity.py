@@ -305,18 +305,21 @@ def channel_results(m, top_wall_u, bottom_wall_T):
             "jump": np.polyval(Tfit, 0.0) - bottom_wall_T}
 
 
-def result_errors(got, want, atol):
+def result_errors(got, want, atol, atol_T=None):
     """Relative error of each result after removing an absolute rounding
-    floor atol (profiles: relative to their largest magnitude; T: relative
-    to the temperature rise above the wall)."""
-    def rel(diff, scale):
-        return max(diff - atol, 0.0) / scale
+    floor atol (atol_T for the temperature and its jump, default atol)
+    (profiles: relative to their largest magnitude; T: relative to the
+    temperature rise above the wall)."""
+    atol_T = atol if atol_T is None else atol_T
+
+    def rel(diff, scale, a=atol):
+        return max(diff - a, 0.0) / scale
     out = {}
     for k in ("u", "sxy", "qy"):
         out[k] = rel(np.abs(got[k] - want[k]).max(), np.abs(want[k]).max())
-    out["T"] = rel(np.abs(got["T"] - want["T"]).max(), np.abs(want["T"] - 1.0).max())
-    for k in ("slip", "jump"):
-        out[k] = rel(abs(got[k] - want[k]), abs(want[k]))
+    out["T"] = rel(np.abs(got["T"] - want["T"]).max(), np.abs(want["T"] - 1.0).max(), atol_T)
+    out["slip"] = rel(abs(got["slip"] - want["slip"]), abs(want["slip"]))
+    out["jump"] = rel(abs(got["jump"] - want["jump"]), abs(want["jump"]), atol_T)
     return out
 
 
@@ -339,6 +342,11 @@ C5_TOL = {"fp64": dict(rest=1e-12), "fp32": dict(rest=1e-5, qy=FP32_Q_TOL),
           "fp32s": dict(rest=1e-5), "fp16": dict(rest=1e-3, qy=5e-3),
           "bf16": dict(rest=1e-2, qy=5e-2)}
 C5_ATOL = {"fp64": 2e-14, "fp32": 1e-9, "fp32s": 1e-9, "fp16": 0.0, "bf16": 0.0}
+# FP32 arithmetic forms theta = T - 1 from sums of deviations times |e|^2
+# (up to 27): ~6e-8 of ~0.05 per node, and the x-invariant flow repeats the
+# same rounding in every column, so the x-average keeps it: a floor of
+# ~3e-9 on T, which is 1e-5 of this run's viscous temperature rise (4e-4)
+C5_ATOL_T = {"fp32": 1e-8}
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32s", "fp16", "bf16"])
@@ -357,7 +365,7 @@ def test_c5_full_size_results(c5_reference, prec):
         for k in ("ux", "T", "sxy", "qy"):
             assert np.abs(m[k] - m[k][:, :1]).max() == 0.0, k   # exactly x-invariant
     res = channel_results(m, c["top"][0], c["bottom"][2])
-    errs = result_errors(res, c5_reference, C5_ATOL[prec])
+    errs = result_errors(res, c5_reference, C5_ATOL[prec], C5_ATOL_T.get(prec))
     say("   errors", {k: "%.2e" % v for k, v in errs.items()})
     say("   errors without the floor",
         {k: "%.2e" % v for k, v in result_errors(res, c5_reference, 0.0).items()})
