@@ -179,14 +179,8 @@ bool fill_tables(lbm_ctx* c, Tables* t) {
       positive = positive && t->gt[q] > 0;
     }
   }
-  // 16-bit codecs: FP16 keeps (f - w) * 2^12 (deviations |f - w| < 1 fit its
-  // range, small ones stay normal); BF16 has FP32's range, scale 1.
-  // Wb/Wt enter the pooled mass as M = W + sum of deviations.
   t->ab = c->alpha_b;
   t->at = c->alpha_t;
-  const float S = c->prec == kFP16 ? 4096.0f : 1.0f;
-  t->dec = 1.0f / S;
-  t->enc = S;
   return positive;
 }
 

@@ -68,8 +68,8 @@ __device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
 
 // Storage <-> arithmetic.  Every format holds the deviation g = f - w_q from
 // the rest state, so rounding acts on the (small) deviation, not on f.
-// 16-bit formats hold h = g * S for a per-format power of two S
-// (Tables::dec = 1/S, enc = S) and decode to float.  They round
+// 16-bit formats hold h = g * S for a per-format power of two S (a
+// compile-time constant: 2^12 for FP16, 1 for BF16) and decode to float.  They round
 // stochastically: a slowly varying population rounded to nearest is rounded
 // the same way every step, and that bias accumulates in the conserved
 // moments over the flow's momentum-diffusion time; unbiased rounding leaves a
@@ -100,6 +100,7 @@ struct CF64 {
   using R = double;
   static constexpr uint32_t B = 8;
   static constexpr bool kRandom = false;
+  static constexpr int kRandBits = 0;
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
   }
@@ -115,6 +116,7 @@ struct CF32 {
   using R = float;
   static constexpr uint32_t B = 4;
   static constexpr bool kRandom = false;
+  static constexpr int kRandBits = 0;
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
   }
@@ -135,6 +137,7 @@ struct CF32S {
   using R = double;
   static constexpr uint32_t B = 4;
   static constexpr bool kRandom = true;
+  static constexpr int kRandBits = 29;
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return double(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0)));
   }
@@ -158,21 +161,23 @@ struct CF32S {
   }
 };
 
+// BF16 has FP32's exponent range: the deviations are stored unscaled.
 struct CBF16 {
   using S = uint16_t;
   using R = float;
   static constexpr uint32_t B = 2;
   static constexpr bool kRandom = true;
-  __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables* t) {
+  static constexpr int kRandBits = 16;
+  __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
-    return __uint_as_float(h << 16) * t->dec;
+    return __uint_as_float(h << 16);
   }
   // Stochastic rounding to the 8-bit significand: add 16 random bits below
   // the kept ones to the magnitude, truncate.
   template <int POL>
-  __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables* t,
+  __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*,
                             uint32_t rnd) {
-    const uint32_t u = __float_as_uint(g * t->enc);
+    const uint32_t u = __float_as_uint(g);
     uint32_t mag = u & 0x7fffffffu;
     if (mag > 0x7f800000u)
       mag = 0x7fc00000u;  // keep NaN a NaN
@@ -183,23 +188,30 @@ struct CBF16 {
   }
 };
 
+// FP16 keeps (f - w) * 2^12: deviations |f - w| < 1 fit its range (65504)
+// and small ones stay above its normal limit 2^-14.  The scale is a
+// compile-time constant: a scale read from memory would have to be re-read
+// after every population store (the stores may alias it), each re-read
+// waiting for all stores in flight.
 struct CFP16 {
   using S = _Float16;
   using R = float;
   static constexpr uint32_t B = 2;
   static constexpr bool kRandom = true;
-  __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables* t) {
+  static constexpr int kRandBits = 13;
+  static constexpr float kScale = 4096.0f;
+  __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
-    return float(__builtin_bit_cast(_Float16, h)) * t->dec;
+    return float(__builtin_bit_cast(_Float16, h)) * (1.0f / kScale);
   }
   // Stochastic rounding to FP16's 10-bit significand in its normal range
   // [2^-14, 65504]: add 13 random bits below the kept ones to the float's
   // magnitude and truncate, which leaves a value FP16 holds exactly.  Below
   // the normal range (rare with the scale S) round to nearest even.
   template <int POL>
-  __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables* t,
+  __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*,
                             uint32_t rnd) {
-    const uint32_t u = __float_as_uint(g * t->enc);
+    const uint32_t u = __float_as_uint(g * kScale);
     uint32_t mag = u & 0x7fffffffu;
     if (mag >= 0x38800000u && mag < 0x477fe000u)
       mag = (mag + (rnd & 0x1fffu)) & 0xffffe000u;
@@ -664,12 +676,21 @@ __device__ __forceinline__ void store(const typename C::R (&f)[L::Q], const Step
                                       uint32_t n) {
   const Rsrc fout = plane_set<L, C>(a.fout, a.plane);
   const uint32_t pb = uint32_t(a.plane) * C::B;
-  // counter for the stochastic rounding of 16-bit formats: (node, q, step)
+  // counter for the stochastic rounding of the rounded formats: (node, q,
+  // step).  Formats that need at most 16 random bits take one 32-bit hash
+  // per pair of velocities (low half for even q, high half for odd q).
   const uint32_t key =
       C::kRandom ? mix32(a.step * 0x9e3779b9u + a.seed) ^ (n * uint32_t(L::Q)) : 0u;
+  uint32_t hpair = 0u;
   auto body = [&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    const uint32_t rnd = C::kRandom ? mix32(key + uint32_t(q) * 0x85ebca77u) : 0u;
+    uint32_t rnd = 0u;
+    if constexpr (C::kRandom && C::kRandBits <= 16) {
+      if constexpr (q % 2 == 0) hpair = mix32(key + uint32_t(q / 2) * 0x85ebca77u);
+      rnd = q % 2 == 0 ? hpair : hpair >> 16;
+    } else if constexpr (C::kRandom) {
+      rnd = mix32(key + uint32_t(q) * 0x85ebca77u);
+    }
     C::template st<POL>(fout, n * C::B, uint32_t(q) * pb, f[q], a.tab, rnd);
   };
   static_for<0, L::Q>(body);

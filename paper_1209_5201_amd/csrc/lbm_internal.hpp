@@ -28,9 +28,6 @@ struct Tables {
                       // (velocity, row) pairs that cross each wall
   double ab, at;      // accommodation of each wall: the diffuse share of the
                       // scattering kernel R = a R_D + (1 - a) R_specular
-  float dec;          // 16-bit codecs: g = h * dec
-  float enc;          //                h = g * enc
-  float pad[2];
 };
 
 struct StepArgs {
