@@ -22,6 +22,8 @@ SOURCES = [os.path.join(CSRC, "lbm_set_%s_%s%s.hip" % (s, p, f))
            for f in ("", "_force")] + \
     [os.path.join(CSRC, "lbm_batch_%s%s.hip" % (p, f))
      for p in ("fp64", "fp32", "bf16", "fp16", "fp32s") for f in ("", "_force")] + \
+    [os.path.join(CSRC, "lbm_batch_%s_3d%s.hip" % (p, f))
+     for p in ("fp64", "fp32s") for f in ("", "_force")] + \
     [os.path.join(CSRC, "lbm_dispatch.hip"), os.path.join(CSRC, "lbm_api.cpp")]
 
 HIPCC_FLAGS = [

@@ -544,16 +544,18 @@ int lbm_batch_run(lbm_ctx* const* ctxs, int n_ctx, const int64_t* budgets, int64
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return LBM_EINVAL;  // one context twice would race
   }
-  // group the cases by storage format and force variant: one launch per
-  // group present (group = format + kPrecCount * has_force)
-  constexpr int kGroups = 2 * kPrecCount;
+  // group the cases by storage format, force variant and, for the formats
+  // whose large set has its own kernel instance, set class: one launch per
+  // group present (group = format + kPrecCount * (has_force + 2 * large))
+  constexpr int kGroups = 4 * kPrecCount;
   std::vector<CaseDesc> desc(n_ctx);
   std::vector<int> pos(n_ctx), fmt(n_ctx);
   int start[kGroups + 1] = {};
   for (int i = 0; i < n_ctx; ++i) {
     const lbm_ctx* c = ctxs[i];
     const bool force = c->acc[0] != 0.0 || c->acc[1] != 0.0 || c->acc[2] != 0.0;
-    fmt[i] = c->prec + (force ? kPrecCount : 0);
+    const bool large = batch_splits_sets(c->prec) && c->lattice == LBM_D3Q121;
+    fmt[i] = c->prec + kPrecCount * ((force ? 1 : 0) + (large ? 2 : 0));
   }
   if (!plan_groups(fmt.data(), n_ctx, kGroups, start, pos.data())) return LBM_EINVAL;
   for (int i = 0; i < n_ctx; ++i) {
@@ -593,7 +595,8 @@ int lbm_batch_run(lbm_ctx* const* ctxs, int n_ctx, const int64_t* budgets, int64
     const int cnt = start[p + 1] - start[p];
     if (cnt == 0) continue;
     if (cnt < 0 || start[p] + cnt > n_ctx) return LBM_EINVAL;  // grouping is inconsistent
-    if (!hip_ok(launch_batch(p % kPrecCount, p >= kPrecCount, ddesc + start[p], cnt,
+    const int v = p / kPrecCount;
+    if (!hip_ok(launch_batch(p % kPrecCount, (v & 1) != 0, (v & 2) != 0, ddesc + start[p], cnt,
                              dout + start[p], stream)))
       return LBM_EDEVICE;
   }

@@ -1,6 +1,6 @@
-// Batched persistent small-case kernel, FP16 storage (all velocity sets), body-force variant.
+// Batched persistent small-case kernel, FP16 deviation storage (all velocity sets), body-force variant.
 #define LBM_DEFINE_BATCH
 #include "lbm_device.hpp"
 
-template hipError_t lbm::dev::batch_launch<lbm::dev::CFP16, true>(const lbm::CaseDesc*, int,
-                                                       lbm::CaseOut*, hipStream_t);
+template hipError_t lbm::dev::batch_launch<lbm::dev::CFP16, true, 7>(const lbm::CaseDesc*, int,
+                                                              lbm::CaseOut*, hipStream_t);

@@ -2,5 +2,5 @@
 #define LBM_DEFINE_BATCH
 #include "lbm_device.hpp"
 
-template hipError_t lbm::dev::batch_launch<lbm::dev::CF32, false>(const lbm::CaseDesc*, int,
-                                                       lbm::CaseOut*, hipStream_t);
+template hipError_t lbm::dev::batch_launch<lbm::dev::CF32, false, 7>(const lbm::CaseDesc*, int,
+                                                              lbm::CaseOut*, hipStream_t);

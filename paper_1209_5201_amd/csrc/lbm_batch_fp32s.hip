@@ -1,7 +1,6 @@
-// Batched persistent small-case kernel, FP32 storage with FP64 arithmetic
-// (all velocity sets).
+// Batched persistent small-case kernel, FP32 storage with FP64 arithmetic (2-D velocity sets).
 #define LBM_DEFINE_BATCH
 #include "lbm_device.hpp"
 
-template hipError_t lbm::dev::batch_launch<lbm::dev::CF32S, false>(const lbm::CaseDesc*, int,
-                                                        lbm::CaseOut*, hipStream_t);
+template hipError_t lbm::dev::batch_launch<lbm::dev::CF32S, false, 3>(const lbm::CaseDesc*, int,
+                                                              lbm::CaseOut*, hipStream_t);

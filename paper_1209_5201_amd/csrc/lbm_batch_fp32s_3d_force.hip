@@ -1,0 +1,6 @@
+// Batched persistent small-case kernel, FP32 storage with FP64 arithmetic (D3Q121), body-force variant.
+#define LBM_DEFINE_BATCH
+#include "lbm_device.hpp"
+
+template hipError_t lbm::dev::batch_launch<lbm::dev::CF32S, true, 4>(const lbm::CaseDesc*, int,
+                                                              lbm::CaseOut*, hipStream_t);

@@ -1,6 +1,6 @@
-// Batched persistent small-case kernel, FP64 storage (all velocity sets).
+// Batched persistent small-case kernel, FP64 storage (2-D velocity sets).
 #define LBM_DEFINE_BATCH
 #include "lbm_device.hpp"
 
-template hipError_t lbm::dev::batch_launch<lbm::dev::CF64, false>(const lbm::CaseDesc*, int,
-                                                       lbm::CaseOut*, hipStream_t);
+template hipError_t lbm::dev::batch_launch<lbm::dev::CF64, false, 3>(const lbm::CaseDesc*, int,
+                                                              lbm::CaseOut*, hipStream_t);

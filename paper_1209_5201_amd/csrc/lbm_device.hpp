@@ -853,11 +853,31 @@ __device__ __forceinline__ void residual_terms(const double* mom, double* snap, 
 // kernel and the case stops once the residual is below its tolerance.  A
 // case's arithmetic and stopping point depend only on its own data, so its
 // result is the same alone and in any mix, and whatever its step budget.
+// One step of one case's nodes by the workgroup (the ghost-column ratios
+// already in LDS).  MOM: the last step of a window, which also writes the
+// output fields; its own loop, so that the populations of the two variants
+// never share live ranges (one loop with both would hold more registers).
+template <class L, class C, bool FORCE, bool MOM>
+__device__ __forceinline__ void case_nodes(const StepArgs& a, int nodes, const double* ratio_s) {
+  using R = typename C::R;
+  constexpr int NS = max_ex<L>();
+  for (int n = threadIdx.x; n < nodes; n += kBatchBlock) {
+    const int y = n / a.nx;
+    const int x = n - y * a.nx;
+    int xw[2 * NS + 1];
+    wrapped_columns<NS, false>(x, a.nx, xw);
+    R f[L::Q];
+    pull<L, C>(f, a, y, xw,
+               [&](int wall, int ex) { return ratio_s[wall * a.nx + xw[ex + NS]]; });
+    wall_specular<L, C>(f, a, y, xw);
+    relax<L, R, MOM, FORCE>(f, a, a.mom, nodes, n);
+    store<L, C, kStoreCached>(f, a, uint32_t(n));
+  }
+}
+
 template <class L, class C, bool FORCE>
 __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, double* ratio_s,
                                          double (*red)[kBatchBlock]) {
-  using R = typename C::R;
-  constexpr int NS = max_ex<L>();
   StepArgs a = cd.a;
   const int nodes = a.nx * a.ny;
   const int lane = int(threadIdx.x & 63);
@@ -882,22 +902,10 @@ __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, doubl
           ratio_s[p] = top ? (a.tab->Wt + M) / a.tab->Dt : (a.tab->Wb + M) / a.tab->Db;
       }
       __syncthreads();
-      const bool last = s == W - 1;
-      for (int n = threadIdx.x; n < nodes; n += kBatchBlock) {
-        const int y = n / a.nx;
-        const int x = n - y * a.nx;
-        int xw[2 * NS + 1];
-        wrapped_columns<NS, false>(x, a.nx, xw);
-        R f[L::Q];
-        pull<L, C>(f, a, y, xw,
-                   [&](int wall, int ex) { return ratio_s[wall * a.nx + xw[ex + NS]]; });
-        wall_specular<L, C>(f, a, y, xw);
-        if (last)
-          relax<L, R, true, FORCE>(f, a, a.mom, nodes, n);
-        else
-          relax<L, R, false, FORCE>(f, a);
-        store<L, C, kStoreCached>(f, a, uint32_t(n));
-      }
+      if (s == W - 1)
+        case_nodes<L, C, FORCE, true>(a, nodes, ratio_s);
+      else
+        case_nodes<L, C, FORCE, false>(a, nodes, ratio_s);
       __syncthreads();
       cur ^= 1;
     }
@@ -929,16 +937,29 @@ __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, doubl
   }
 }
 
-template <class C, bool FORCE>
+// SETS: bit mask of the velocity sets the instance carries (1 D2Q16, 2
+// D2Q17, 4 D3Q121).  A kernel's registers are those of its largest set, so
+// the double-precision formats keep the large set in an instance of its own
+// (in one instance with the others its FP64 path spills to scratch and slows
+// every case).  A case of a set the instance does not carry reports failure.
+template <class C, bool FORCE, int SETS>
 __global__ __launch_bounds__(kBatchBlock) void batch_kernel(const CaseDesc* __restrict__ cases,
                                                             CaseOut* out) {
   __shared__ double ratio_s[2 * kBatchMaxNx];
   __shared__ double red[4][kBatchBlock];
   const CaseDesc& cd = cases[blockIdx.x];
-  switch (cd.lattice) {
-    case 0: run_case<D2Q16, C, FORCE>(cd, out, ratio_s, red); break;
-    case 1: run_case<D2Q17, C, FORCE>(cd, out, ratio_s, red); break;
-    case 2: run_case<D3Q121, C, FORCE>(cd, out, ratio_s, red); break;
+  const int lat = cd.lattice;
+  if (lat == 0 && (SETS & 1)) {
+    if constexpr ((SETS & 1) != 0) run_case<D2Q16, C, FORCE>(cd, out, ratio_s, red);
+  } else if (lat == 1 && (SETS & 2)) {
+    if constexpr ((SETS & 2) != 0) run_case<D2Q17, C, FORCE>(cd, out, ratio_s, red);
+  } else if (lat == 2 && (SETS & 4)) {
+    if constexpr ((SETS & 4) != 0) run_case<D3Q121, C, FORCE>(cd, out, ratio_s, red);
+  } else if (threadIdx.x == 0) {
+    out[blockIdx.x].residual = __builtin_nan("");
+    out[blockIdx.x].mass = __builtin_nan("");
+    out[blockIdx.x].steps = 0.0;
+    out[blockIdx.x].state = -1.0;
   }
 }
 
@@ -1003,39 +1024,48 @@ hipError_t SetOps<L, C, FORCE>::init(const StepArgs& a, const double* fields, hi
 #endif
 
 // Batched persistent launch of one storage format (lbm_batch_*.hip).
-template <class C, bool FORCE>
+template <class C, bool FORCE, int SETS>
 hipError_t batch_launch(const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s);
 
 #ifdef LBM_DEFINE_BATCH
-template <class C, bool FORCE>
+template <class C, bool FORCE, int SETS>
 hipError_t batch_launch(const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s) {
   clear_stale_error();
-  hipLaunchKernelGGL((batch_kernel<C, FORCE>), dim3(unsigned(ncase)), dim3(kBatchBlock), 0, s,
-                     cases, out);
+  hipLaunchKernelGGL((batch_kernel<C, FORCE, SETS>), dim3(unsigned(ncase)), dim3(kBatchBlock), 0,
+                     s, cases, out);
   return hipGetLastError();
 }
 #endif
 
-extern template hipError_t batch_launch<CF64, false>(const CaseDesc*, int, CaseOut*,
-                                                       hipStream_t);
-extern template hipError_t batch_launch<CF64, true>(const CaseDesc*, int, CaseOut*,
-                                                       hipStream_t);
-extern template hipError_t batch_launch<CF32, false>(const CaseDesc*, int, CaseOut*,
-                                                       hipStream_t);
-extern template hipError_t batch_launch<CF32, true>(const CaseDesc*, int, CaseOut*,
-                                                       hipStream_t);
-extern template hipError_t batch_launch<CBF16, false>(const CaseDesc*, int, CaseOut*,
-                                                       hipStream_t);
-extern template hipError_t batch_launch<CBF16, true>(const CaseDesc*, int, CaseOut*,
-                                                       hipStream_t);
-extern template hipError_t batch_launch<CFP16, false>(const CaseDesc*, int, CaseOut*,
-                                                       hipStream_t);
-extern template hipError_t batch_launch<CFP16, true>(const CaseDesc*, int, CaseOut*,
-                                                       hipStream_t);
-extern template hipError_t batch_launch<CF32S, false>(const CaseDesc*, int, CaseOut*,
-                                                       hipStream_t);
-extern template hipError_t batch_launch<CF32S, true>(const CaseDesc*, int, CaseOut*,
-                                                       hipStream_t);
+
+extern template hipError_t batch_launch<CF64, false, 3>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF64, false, 4>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF64, true, 3>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF64, true, 4>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF32, false, 7>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF32, true, 7>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CBF16, false, 7>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CBF16, true, 7>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CFP16, false, 7>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CFP16, true, 7>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF32S, false, 3>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF32S, false, 4>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF32S, true, 3>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
+extern template hipError_t batch_launch<CF32S, true, 4>(const CaseDesc*, int,
+                                                           CaseOut*, hipStream_t);
 
 extern template struct SetOps<D2Q16, CF64, false>;
 extern template struct SetOps<D2Q16, CF64, true>;

@@ -52,10 +52,22 @@ hipError_t by_prec(int prec, const StepArgs& a, F&& fn) {
   return a.force ? by_prec_f<L, true>(prec, fn) : by_prec_f<L, false>(prec, fn);
 }
 
+// all sets in one instance (SETS = 7)
 template <class C>
 hipError_t batch_of(bool force, const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s) {
-  return force ? dev::batch_launch<C, true>(cases, ncase, out, s)
-               : dev::batch_launch<C, false>(cases, ncase, out, s);
+  return force ? dev::batch_launch<C, true, 7>(cases, ncase, out, s)
+               : dev::batch_launch<C, false, 7>(cases, ncase, out, s);
+}
+
+// the 2-D sets (SETS = 3) or the large set (SETS = 4) in separate instances
+template <class C>
+hipError_t batch_of_split(bool force, bool large, const CaseDesc* cases, int ncase,
+                          CaseOut* out, hipStream_t s) {
+  if (large)
+    return force ? dev::batch_launch<C, true, 4>(cases, ncase, out, s)
+                 : dev::batch_launch<C, false, 4>(cases, ncase, out, s);
+  return force ? dev::batch_launch<C, true, 3>(cases, ncase, out, s)
+               : dev::batch_launch<C, false, 3>(cases, ncase, out, s);
 }
 
 template <class F>
@@ -108,15 +120,17 @@ hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch(int prec, bool force, const CaseDesc* cases, int ncase, CaseOut* out,
-                        hipStream_t s) {
+bool batch_splits_sets(int prec) { return prec == kFP64 || prec == kFP32S; }
+
+hipError_t launch_batch(int prec, bool force, bool large, const CaseDesc* cases, int ncase,
+                        CaseOut* out, hipStream_t s) {
   if (ncase <= 0 || !cases || !out) return hipErrorInvalidValue;  // one workgroup per case
   switch (prec) {
-    case kFP64: return batch_of<dev::CF64>(force, cases, ncase, out, s);
+    case kFP64: return batch_of_split<dev::CF64>(force, large, cases, ncase, out, s);
     case kFP32: return batch_of<dev::CF32>(force, cases, ncase, out, s);
     case kBF16: return batch_of<dev::CBF16>(force, cases, ncase, out, s);
     case kFP16: return batch_of<dev::CFP16>(force, cases, ncase, out, s);
-    case kFP32S: return batch_of<dev::CF32S>(force, cases, ncase, out, s);
+    case kFP32S: return batch_of_split<dev::CF32S>(force, large, cases, ncase, out, s);
   }
   return hipErrorInvalidValue;
 }

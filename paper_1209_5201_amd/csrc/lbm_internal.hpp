@@ -100,8 +100,12 @@ hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s);
 // case after the first window whose residual is below cases[i].tol; writes
 // each case's fields after its last window, its mass / residual sums into
 // its result block, and out[i].
-hipError_t launch_batch(int prec, bool force, const CaseDesc* cases, int ncase, CaseOut* out,
-                        hipStream_t s);
+// large: for formats with batch_splits_sets, the launch of the large set's
+// cases (else of the 2-D sets' cases); ignored for the other formats, whose
+// one launch takes every set.
+hipError_t launch_batch(int prec, bool force, bool large, const CaseDesc* cases, int ncase,
+                        CaseOut* out, hipStream_t s);
+bool batch_splits_sets(int prec);
 
 // Host helpers (no device work).
 // g^eq_q(u, T) of every velocity with unit density (wall Maxwellians).

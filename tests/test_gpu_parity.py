@@ -228,6 +228,23 @@ def test_mass_conservation_and_rest_state():
         r.close()
 
 
+@pytest.mark.parametrize("lat", LATS)
+@pytest.mark.parametrize("nx", [1, 7, 256])
+def test_thinnest_channel(lat, nx):
+    """ny = 2N, the smallest channel: every row is a wall row of both walls'
+    reach, and the ghost columns wrap on a single column (nx = 1)."""
+    ny = 6
+    say("case thinnest", lat, nx)
+    fields = W.random_fields(nx, ny, seed=12, thermal=(lat == "D3Q121"))
+    g = gpu_case(lat, nx, ny, 0.9, *WALLS[lat], fields=fields)
+    o = oracle_case(lat, nx, ny, 0.9, *WALLS[lat], fields=fields)
+    for t in (1, 30):
+        g.step(t)
+        o.run(t)
+        assert_fields(g.moments(), o.moments(), 1e-12, ctx="t=%d" % o.t)
+    g.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("fp32s", 1e-5)])
 def test_c3_full_size_launch_against_tiled_oracle(prec, tol):
     """The 2048 x 2048 bulk case in the benchmark's launch configuration.
