@@ -40,7 +40,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, published
-KERNEL = "step_rows_kernel<D2Q17, CF32, false>"
+KERNEL = "step_rows_kernel<D2Q17, CF32, false, false>"
 WORKLOAD = "D2Q17 2048x2048 FP32"
 
 
@@ -228,7 +228,7 @@ def main():
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(args.traffic_from[0], args.traffic_from[1],
-                      "step_rows_kernel<lbm::D2Q17, lbm::dev::CF32, false>", KERNEL,
+                      "step_rows_kernel<lbm::D2Q17, lbm::dev::CF32, false, false>", KERNEL,
                       WORKLOAD)
         return
     if args.gpus != 1:
