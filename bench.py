@@ -225,6 +225,12 @@ def main():
     ap.add_argument("--serving-baseline", type=int, default=16)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-precisions", action="store_true")
+    ap.add_argument("--profile-formats", type=int, metavar="STEPS",
+                    help="only run the D3Q121 1024^2 channel STEPS steps in every storage "
+                         "format (a short run to trace under rocprofv3) and exit")
+    ap.add_argument("--profile-serving", type=int, metavar="REQUESTS",
+                    help="only serve the first REQUESTS requests of the serving stream "
+                         "(FP32, all queued at t = 0; a run to trace) and exit")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(args.traffic_from[0], args.traffic_from[1],
@@ -242,6 +248,32 @@ def main():
     import torch
     import paper_1209_5201_amd as lbm
     from paper_1209_5201_amd import workloads as W
+
+    if args.profile_formats:
+        c = W.C5
+        out = {}
+        for prec in ("fp64", "fp32", "fp32s", "bf16", "fp16"):
+            ch = lbm.Channel("D3Q121", c["nx"], c["ny"],
+                             lbm.lbm_tau_from_kn("D3Q121", c["ny"], c["kn"]), c["bottom"],
+                             c["top"], prec=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ch.step(args.profile_formats)
+            torch.cuda.synchronize()
+            out[prec] = round((time.perf_counter() - t0) / args.profile_formats * 1e6, 1)
+            ch.close()
+        print(json.dumps({"workload": "D3Q121 1024x1024 Couette, every format",
+                          "us_per_step": out}), flush=True)
+        return
+    if args.profile_serving:
+        from paper_1209_5201_amd import serve
+        reqs = W.serving_requests(n=args.profile_serving, seed=1, rate=args.serving_rate)
+        res = serve.Server(prec="fp32", window=100, tol=1e-8, keep_profiles=False).run(
+            reqs, realtime=False)
+        print(json.dumps({"workload": "serving stream, first %d requests" % args.profile_serving,
+                          "solves": res["solves"], "solves_per_s": round(res["solves_per_s"], 1),
+                          "launches": res["launches"]}), flush=True)
+        return
 
     torch.cuda.set_device(0)
     cfg = W.C3
