@@ -101,6 +101,7 @@ struct CF64 {
   static constexpr uint32_t B = 8;
   static constexpr bool kRandom = false;
   static constexpr int kRandBits = 0;
+  static constexpr bool kWallRowsFirst = false;  // row order of the row-tiled update
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
   }
@@ -117,6 +118,7 @@ struct CF32 {
   static constexpr uint32_t B = 4;
   static constexpr bool kRandom = false;
   static constexpr int kRandBits = 0;
+  static constexpr bool kWallRowsFirst = false;  // row order of the row-tiled update
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
   }
@@ -138,6 +140,7 @@ struct CF32S {
   static constexpr uint32_t B = 4;
   static constexpr bool kRandom = true;
   static constexpr int kRandBits = 29;
+  static constexpr bool kWallRowsFirst = true;  // row order of the row-tiled update
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return double(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0)));
   }
@@ -168,6 +171,7 @@ struct CBF16 {
   static constexpr uint32_t B = 2;
   static constexpr bool kRandom = true;
   static constexpr int kRandBits = 16;
+  static constexpr bool kWallRowsFirst = true;  // row order of the row-tiled update
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
     return __uint_as_float(h << 16);
@@ -199,6 +203,7 @@ struct CFP16 {
   static constexpr uint32_t B = 2;
   static constexpr bool kRandom = true;
   static constexpr int kRandBits = 13;
+  static constexpr bool kWallRowsFirst = true;  // row order of the row-tiled update
   static constexpr float kScale = 4096.0f;
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
@@ -751,8 +756,17 @@ __global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
   __shared__ double ratio_s[kBlock + 2 * NS];
   const int bpr = a.nx / kBlock;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int y = b / bpr;
-  const int x0 = (b - y * bpr) * kBlock;
+  const int r = b / bpr;
+  // Wall-row blocks also sum the ghost columns (a second round of loads
+  // before the pull), so they take longest.  The 16-bit and FP32-storage
+  // updates schedule the 2N wall rows first, so that they do not form the
+  // grid's tail (measured: D3Q121 BF16 159 -> 138 us, D2Q17 BF16 60 -> 57 us,
+  // FP32 storage -1 to -2 %; none for FP32 and FP64, which keep the plain
+  // order for the cache reuse of neighbouring rows).
+  int y = r;
+  if constexpr (C::kWallRowsFirst)
+    y = r < L::N ? r : r < 2 * L::N ? a.ny - 1 - (r - L::N) : r - L::N;
+  const int x0 = (b - r * bpr) * kBlock;
   const int x = x0 + int(threadIdx.x);
   int xw[2 * NS + 1];
   wrapped_columns<NS, true>(x, a.nx, xw);
