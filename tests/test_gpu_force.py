@@ -133,3 +133,34 @@ def test_force_is_refused_where_it_does_not_apply():
         with pytest.raises(lbm.LbmError):
             ch.set_body_force(*bad)
     ch.close()
+
+
+# 16-bit storage with every wall / collision option at once: the force
+# variant of the 16-bit kernels, partial accommodation and (D3Q121) the
+# viscosity law, against the FP64 oracle, node by node (no averaging).  Bars
+# from the storage rounding of a random start (2^-8 relative per value in
+# BF16, 2^-11 in FP16, accumulated over 40 steps): rho, u, T to 1e-2 / 1e-3
+# of their scale; sigma_xy, the small non-equilibrium part, to 2e-2 / 2e-3
+# (measured: BF16 7-9e-3, FP16 1.0e-3).
+REDUCED16 = {"bf16": (1e-2, 2e-2), "fp16": (1e-3, 2e-3)}
+
+
+@pytest.mark.parametrize("lat", ["D2Q17", "D3Q121"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_16bit_with_force_accommodation_and_law(lat, prec):
+    say("case 16-bit options", lat, prec)
+    w = 0.7 if lat == "D3Q121" else None
+    rho, ux, uy, T = W.random_fields(256, 16, seed=17, thermal=(lat == "D3Q121"))
+    g = lbm.Channel(lat, 256, 16, 0.8, *WALLS[lat], prec=prec, accommodation=(0.6, 0.9),
+                    force=FORCE[lat], viscosity_exp=w)
+    g.init(rho=rho, ux=ux, uy=uy, T=T)
+    o = O.OracleCase(lat, 256, 16, 0.8, *WALLS[lat], rho0=rho,
+                     u0=np.stack([ux, uy, np.zeros_like(ux)]), T0=T,
+                     accommodation=(0.6, 0.9), force=FORCE[lat], viscosity_exp=w)
+    g.step(40)
+    o.run(40)
+    got, want = g.moments(), o.moments()
+    bar, bar_s = REDUCED16[prec]
+    assert max_err(got, want, 0.0, FIELDS[:5]) <= bar
+    assert max_err(got, want, 0.0, ("sxy",)) <= bar_s
+    g.close()
