@@ -52,6 +52,51 @@ __device__ __forceinline__ R add_scaled(R acc, R v) {
   else return acc + R(K) * v;
 }
 
+// k * v for a small compile-time integer k (the first term of a sum: no
+// addition to a zero, which IEEE arithmetic cannot drop because of -0).
+template <int K, class R>
+__device__ __forceinline__ R scaled(R v) {
+  if constexpr (K == 1) return v;
+  else if constexpr (K == -1) return -v;
+  else return R(K) * v;
+}
+
+// acc + k * v, or k * v alone when FIRST (acc not yet assigned).
+template <int K, bool FIRST, class R>
+__device__ __forceinline__ R accum(R acc, R v) {
+  if constexpr (K == 0) return acc;
+  else if constexpr (FIRST) return scaled<K>(v);
+  else return add_scaled<K>(acc, v);
+}
+
+// e_x a + e_y b + e_z c for a compile-time integer vector e.
+template <int EX, int EY, int EZ, class R>
+__device__ __forceinline__ R dot_e(R a, R b, R c) {
+  if constexpr (EX != 0) return add_scaled<EZ>(add_scaled<EY>(scaled<EX>(a), b), c);
+  else if constexpr (EY != 0) return add_scaled<EZ>(scaled<EY>(b), c);
+  else if constexpr (EZ != 0) return scaled<EZ>(c);
+  else return R(0);
+}
+
+// Index of the velocity -c_q, and the first velocity with a nonzero
+// component k (k = 3: nonzero |c|^2).
+template <class L>
+constexpr int opposite(int q) {
+  for (int p = 0; p < L::Q; ++p)
+    if (L::E[p][0] == -L::E[q][0] && L::E[p][1] == -L::E[q][1] && L::E[p][2] == -L::E[q][2])
+      return p;
+  return -1;
+}
+template <class L>
+constexpr int first_nonzero(int k) {
+  for (int p = 0; p < L::Q; ++p) {
+    const int v = k < 3 ? L::E[p][k]
+                        : L::E[p][0] * L::E[p][0] + L::E[p][1] * L::E[p][1] + L::E[p][2] * L::E[p][2];
+    if (v != 0) return p;
+  }
+  return -1;
+}
+
 // ---------------------------------------------------------------- codecs --
 // Population planes are accessed through buffer resources (one descriptor
 // per plane set): the per-velocity plane offset q * plane * bytes is a
@@ -325,6 +370,40 @@ struct EqCoef {
     else if constexpr (L::EQ == 3) return K0 + x * (K1 + x * (K2 + x * k3));
     else return K0 + x * (K1 + x * K2);
   }
+
+  // poly<EE> at x and at -x (velocities c and -c): the parts even and odd in
+  // x are shared.
+  template <int EE>
+  __host__ __device__ void poly_pair(R x, R& plus, R& minus) const {
+    constexpr R cc = R(L::R * L::R * EE);
+    R K0, K1, K2;
+    if constexpr (L::THERMAL) {
+      K0 = k0a + cc * (k0b + cc * k0c);
+      K1 = k1a + cc * k1b;
+      K2 = k2a + cc * k2b;
+    } else {
+      K0 = k0a;
+      K1 = k1a;
+      K2 = k2a;
+    }
+    const R x2 = x * x;
+    R even, odd;
+    if constexpr (L::EQ >= 4) {
+      even = K0 + x2 * (K2 + x2 * k4);
+      odd = K1 + x2 * k3;
+    } else if constexpr (L::EQ == 3) {
+      even = K0 + x2 * K2;
+      odd = K1 + x2 * k3;
+    } else {
+      even = K0 + x2 * K2;
+      odd = K1;
+    }
+    plus = even + x * odd;
+    minus = even - x * odd;
+  }
+
+  // poly at the rest velocity (c = 0, x = 0)
+  __host__ __device__ R poly0() const { return k0a; }
 };
 
 template <class R>
@@ -343,11 +422,12 @@ __device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
     constexpr int q = decltype(qc)::value;
     constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
     const R v = R(g[q]);
-    drho += v;
-    mx = add_scaled<ex>(mx, v);
-    my = add_scaled<ey>(my, v);
-    mz = add_scaled<ez>(mz, v);
-    if constexpr (L::THERMAL) e2 = add_scaled<ex * ex + ey * ey + ez * ez>(e2, v);
+    drho = q == 0 ? v : drho + v;
+    mx = accum<ex, q == first_nonzero<L>(0)>(mx, v);
+    my = accum<ey, q == first_nonzero<L>(1)>(my, v);
+    mz = accum<ez, q == first_nonzero<L>(2)>(mz, v);
+    if constexpr (L::THERMAL)
+      e2 = accum<ex * ex + ey * ey + ez * ez, q == first_nonzero<L>(3)>(e2, v);
   };
   static_for<0, L::Q>(body);
   Macro<R> m;
@@ -357,9 +437,9 @@ __device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
   constexpr R r = R(L::R);
   m.ux = r * mx * inv;
   m.uy = r * my * inv;
-  m.uz = r * mz * inv;
+  m.uz = L::D == 3 ? r * mz * inv : R(0);
   if constexpr (L::THERMAL) {
-    const R uu = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+    const R uu = L::D == 3 ? m.ux * m.ux + m.uy * m.uy + m.uz * m.uz : m.ux * m.ux + m.uy * m.uy;
     m.th = (R(L::R * L::R) * e2 - m.rho * uu - R(L::D) * drho) * (inv * R(1.0 / L::D));
   } else {
     m.th = R(0);
@@ -399,7 +479,7 @@ __device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* m
     m.uz += R(0.5) * faz;
     if constexpr (L::THERMAL) m.th += (fax * fax + fay * fay + faz * faz) * R(0.25 / L::D);
   }
-  const R uu = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+  const R uu = L::D == 3 ? m.ux * m.ux + m.uy * m.uy + m.uz * m.uz : m.ux * m.ux + m.uy * m.uy;
   const auto k = EqCoef<L, R>::make(m.rho, m.drho, uu, m.th);
   constexpr R r = R(L::R);
   const R sx = r * m.ux, sy = r * m.uy, sz = r * m.uz;
@@ -414,15 +494,11 @@ __device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* m
   }
   const R au = fax * m.ux + fay * m.uy + faz * m.uz;
   R sxy = 0, qx = 0, qy = 0, qz = 0;
-  auto body = [&](auto qc) {
+  // velocity q at x = c_q.u, with geq = f^eq_q - w_q
+  auto finish = [&](auto qc, R x, R geq) {
     constexpr int q = decltype(qc)::value;
     constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
     constexpr int EE = ex * ex + ey * ey + ez * ez;
-    R x = R(0);
-    x = add_scaled<ex>(x, sx);
-    x = add_scaled<ey>(x, sy);
-    x = add_scaled<ez>(x, sz);
-    const R geq = R(L::W[q]) * k.template poly<EE>(x);
     R F = R(0);
     if constexpr (FORCE) {
       R ac = R(0);
@@ -446,6 +522,23 @@ __device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* m
       g[q] = g[q] + omega * (geq - g[q]) + kf * F;
     else
       g[q] = g[q] + omega * (geq - g[q]);
+  };
+  // The velocities come in pairs c, -c (and the rest velocity): x changes
+  // sign within a pair, and f^eq's even and odd parts in x are shared.
+  auto body = [&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int o = opposite<L>(q);
+    static_assert(o >= 0, "velocity set not closed under c -> -c");
+    constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
+    if constexpr (o == q) {
+      finish(qc, R(0), R(L::W[q]) * k.poly0());
+    } else if constexpr (q < o) {
+      const R x = dot_e<ex, ey, ez>(sx, sy, sz);
+      R plus, minus;
+      k.template poly_pair<ex * ex + ey * ey + ez * ez>(x, plus, minus);
+      finish(qc, x, R(L::W[q]) * plus);
+      finish(std::integral_constant<int, o>{}, -x, R(L::W[o]) * minus);
+    }
   };
   static_for<0, L::Q>(body);
   if constexpr (MOM) {
