@@ -20,7 +20,9 @@ HBM roofline of the fused update kernel (algorithmic bytes 2*Q*4 per node;
 kernel time from a HIP event pair on the library's stream around the timed
 K steps, less a one-step call that holds the field-writing launch and the
 reductions, over K - 1), and the FP64 oracle timed on the host on a bounded
-sample of the same workload.
+sample of the same workload.  Beside it, a practical ceiling measured in the
+same run (libceiling.so): the update's own pull-and-store pattern with no
+collision arithmetic, and a copy, both alternating between two buffers.
 
     python bench.py --traffic-from FETCH.csv WRITE.csv
 rewrites profiles/traffic.json from two rocprofv3 --pmc counter files
@@ -172,7 +174,9 @@ def precision_table(torch, steps_2d: int = 200, steps_3d: int = 60):
     """MLUPS and algorithmic HBM rate of the fused update per velocity set and
     storage format: the bulk D2Q17 2048^2 case and the D3Q121 1024^2 case
     (walls -0.1 / +0.1, Kn 0.05).  Wall clock over back-to-back steps (one
-    launch per step); fields refreshed once at the end."""
+    launch per step); fields refreshed once at the end.  Each row also gives
+    the same-run pull ceiling for its element size and the fraction of it the
+    update reaches."""
     import paper_1209_5201_amd as lbm
     from paper_1209_5201_amd import workloads as W
     rows = []
@@ -180,6 +184,7 @@ def precision_table(torch, steps_2d: int = 200, steps_3d: int = 60):
             ("D2Q17", 2048, 2048, steps_2d, (W.C3["bottom"], W.C3["top"])),
             ("D3Q121", W.C5["nx"], W.C5["ny"], steps_3d, (W.C5["bottom"], W.C5["top"]))):
         Q = lbm.lbm_lattice_info(lat)["Q"]
+        ceilings = {}   # pull ceiling per element size, for this set and grid
         for prec, b in (("fp64", 8), ("fp32", 4), ("fp32s", 4), ("bf16", 2), ("fp16", 2)):
             ch = lbm.Channel(lat, nx, ny, lbm.lbm_tau_from_kn(lat, ny, 0.05), *walls, prec=prec)
             ch.step(10)
@@ -190,9 +195,14 @@ def precision_table(torch, steps_2d: int = 200, steps_3d: int = 60):
             dt = (time.perf_counter() - t0) / steps
             ch.close()
             gbps = 2.0 * Q * b * nx * ny / dt / 1e9
-            rows.append({"lattice": lat, "grid": "%dx%d" % (nx, ny), "precision": prec,
-                         "MLUPS": round(nx * ny / dt / 1e6, 1), "us_per_step": round(dt * 1e6, 1),
-                         "alg_GBps": round(gbps, 1), "frac_hbm": round(gbps / HBM_PEAK_GBPS, 3)})
+            row = {"lattice": lat, "grid": "%dx%d" % (nx, ny), "precision": prec,
+                   "MLUPS": round(nx * ny / dt / 1e6, 1), "us_per_step": round(dt * 1e6, 1),
+                   "alg_GBps": round(gbps, 1), "frac_hbm": round(gbps / HBM_PEAK_GBPS, 3)}
+            if b not in ceilings:
+                ceilings[b] = practical_ceiling(lat, nx, ny, elem_bytes=b)["pull_GBps"]
+            row["pull_ceiling_GBps"] = round(ceilings[b], 1)
+            row["frac_of_pull_ceiling"] = round(gbps / ceilings[b], 3)
+            rows.append(row)
     return rows
 
 
@@ -210,6 +220,31 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
     e.record()
     e.synchronize()
     return 2.0 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+
+
+def practical_ceiling(lattice: str, nx: int, ny: int, elem_bytes: int = 4,
+                      reps: int = 50) -> dict:
+    """Bandwidth references from libceiling.so, measured in the same run: the
+    update's own pull-and-store pattern with no collision arithmetic, on
+    elements of the storage format's size, and a 16-byte-per-lane copy of the
+    same state.  Both alternate between
+    two buffers, as the update does; with a fixed source buffer, part of
+    every read would come from the memory-side cache."""
+    import ctypes
+    from paper_1209_5201_amd.lbm import LATTICES
+    path = os.path.join(ROOT, "paper_1209_5201_amd", "libceiling.so")
+    if not os.path.exists(path):
+        raise RuntimeError("libceiling.so is not built (python -m paper_1209_5201_amd.build)")
+    fn = ctypes.CDLL(path).lbm_ceiling
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_double)] * 4
+    out = [ctypes.c_double() for _ in range(4)]
+    rc = fn(LATTICES[lattice], elem_bytes, nx, ny, reps, *[ctypes.byref(v) for v in out])
+    if rc != 0:
+        raise RuntimeError("lbm_ceiling failed (%d)" % rc)
+    pull_us, copy_us, pull_bytes, copy_bytes = (v.value for v in out)
+    return {"pull_GBps": pull_bytes / pull_us / 1e3, "pull_us": pull_us,
+            "copy_GBps": copy_bytes / copy_us / 1e3}
 
 
 def main():
@@ -342,6 +377,13 @@ def main():
         "copy_ref_GBps": round(copy_bandwidth(torch), 1),
         "mass_after": mass,
     }
+    ceil = practical_ceiling(lat, nx, ny)
+    line["practical_ceiling"] = {
+        "kind": "same run, FP32, two buffers alternating: the update's pull-and-store pattern "
+                "with no collision arithmetic (rows N..ny-N-1), and a 16-byte copy of the state",
+        "pull_no_arithmetic_GBps": round(ceil["pull_GBps"], 1),
+        "copy_GBps": round(ceil["copy_GBps"], 1),
+        "kernel_frac_of_pull": round(achieved / ceil["pull_GBps"], 4)}
     ch.close()
     if not args.no_precisions:
         line["precisions"] = precision_table(torch)

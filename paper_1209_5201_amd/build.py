@@ -1,4 +1,6 @@
-"""Builds ``liblbm.so`` (the HIP library for gfx950) in-tree with hipcc.
+"""Builds ``liblbm.so`` (the HIP library for gfx950) in-tree with hipcc,
+and ``libceiling.so``, the bandwidth references that ``bench.py`` reports
+beside the update (``csrc/ceiling_probe.hip``; not used by ``liblbm.so``).
 
     python -m paper_1209_5201_amd.build [--verbose]
 
@@ -16,6 +18,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
+CEILING_LIB = os.path.join(PKG, "libceiling.so")
+CEILING_SOURCES = [os.path.join(CSRC, "ceiling_probe.hip")]
 BUILD = os.path.join(PKG, "_build")
 SOURCES = [os.path.join(CSRC, "lbm_set_%s_%s%s.hip" % (s, p, f))
            for s in ("d3q121", "d2q17", "d2q16") for p in ("fp64", "fp32", "bf16", "fp16", "fp32s")
@@ -51,27 +55,34 @@ def _compile(src: str, verbose: bool):
     return obj, res
 
 
+def _link(objs, out: str):
+    tmp = out + ".tmp%d" % os.getpid()
+    link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
+    res = subprocess.run(link, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("link of %s failed (exit %d)" % (os.path.basename(out), res.returncode))
+    os.replace(tmp, out)
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source (in parallel, one process each) and link."""
+    """Compile every source (in parallel, one process each) and link both
+    libraries; returns the path of liblbm.so."""
     from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    workers = max(1, min(len(SOURCES), os.cpu_count() or 1, 16))
+    sources = SOURCES + CEILING_SOURCES
+    workers = max(1, min(len(sources), os.cpu_count() or 1, 16))
     with ThreadPoolExecutor(max_workers=workers) as ex:
-        results = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        results = list(ex.map(lambda s: _compile(s, verbose), sources))
     for obj, res in results:
         if res.returncode != 0:
             sys.stderr.write(res.stdout + res.stderr)
             raise RuntimeError("hipcc failed on %s (exit %d)" % (obj, res.returncode))
         if verbose:
             sys.stderr.write(res.stderr)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + \
-        [obj for obj, _ in results] + ["-o", tmp]
-    res = subprocess.run(link, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("link failed (exit %d)" % res.returncode)
-    os.replace(tmp, LIB)
+    objs = [obj for obj, _ in results]
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], CEILING_LIB)
     return LIB
 
 

@@ -105,3 +105,21 @@ def test_null_context_is_rejected():
     assert lbm.lbm_strerror(lbm.lbm.LBM_ENEGATIVE).startswith("wall Maxwellian")
     lib.lbm_set_accommodation.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
     assert lib.lbm_set_accommodation(None, 0.5, 0.5) == lbm.lbm.LBM_EINVAL
+
+
+def test_ceiling_library_rejects_invalid_arguments_before_device_work():
+    """libceiling.so (the bandwidth references bench.py reports) exports its
+    one entry point and refuses unusable shapes without touching a device."""
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1209_5201_amd", "libceiling.so"))
+    fn = lib.lbm_ceiling
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_double)] * 4
+    out = [ctypes.c_double(-1.0) for _ in range(4)]
+    refs = [ctypes.byref(v) for v in out]
+    assert fn(1, 4, 2048, 2048, 10, None, *refs[1:]) == -1   # null output
+    assert fn(3, 4, 2048, 2048, 10, *refs) == -1             # no such set
+    assert fn(1, 3, 2048, 2048, 10, *refs) == -1             # no such element size
+    assert fn(1, 4, 2000, 2048, 10, *refs) == -1             # nx not a multiple of 256
+    assert fn(1, 2, 2048, 6, 10, *refs) == -1                # ny <= 2N
+    assert fn(2, 8, 1024, 1024, 0, *refs) == -1              # no repetitions
+    assert all(v.value == -1.0 for v in out)
