@@ -189,22 +189,19 @@ struct CF32S {
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return double(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0)));
   }
-  // In the float normal range add 29 random bits below the float's last
-  // significand bit to the double's magnitude and clear them: the result is
-  // a float, converted exactly.  Outside it (zero, tiny values) round to
-  // nearest.
+  // Add 29 random bits below the float's last significand bit to the
+  // double's sign-magnitude word (a carry rounds the magnitude up, for
+  // either sign) and clear them.  In the float normal range the result is a
+  // float and the conversion exact; below 2^-126 the conversion rounds the
+  // result once more to the nearest subnormal (no deviation is that small);
+  // zero stays zero, infinity infinity, a quiet NaN a NaN (its top
+  // significand bit survives).
   template <int POL>
   __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*,
                             uint32_t rnd) {
-    uint64_t u = uint64_t(__double_as_longlong(g));
-    const uint64_t mag = u & 0x7fffffffffffffffull;
-    float f;
-    if (mag >= 0x3810000000000000ull && mag < 0x47efffffe0000000ull) {
-      u = (u + uint64_t(rnd & 0x1fffffffu)) & ~uint64_t(0x1fffffffu);
-      f = float(__longlong_as_double((long long)u));
-    } else {
-      f = float(g);
-    }
+    const uint64_t u = (uint64_t(__double_as_longlong(g)) + uint64_t(rnd & 0x1fffffffu)) &
+                       ~uint64_t(0x1fffffffu);
+    const float f = float(__longlong_as_double((long long)u));
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(f), r, vo, so, POL);
   }
 };
@@ -222,18 +219,15 @@ struct CBF16 {
     return __uint_as_float(h << 16);
   }
   // Stochastic rounding to the 8-bit significand: add 16 random bits below
-  // the kept ones to the magnitude, truncate.
+  // the kept ones to the sign-magnitude word (a carry rounds the magnitude
+  // up, for either sign) and keep the top half.  Infinity stays infinity;
+  // a NaN is stored as the quiet NaN.
   template <int POL>
   __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*,
                             uint32_t rnd) {
-    const uint32_t u = __float_as_uint(g);
-    uint32_t mag = u & 0x7fffffffu;
-    if (mag > 0x7f800000u)
-      mag = 0x7fc00000u;  // keep NaN a NaN
-    else if (mag < 0x7f7f0000u)
-      mag = (mag + (rnd & 0xffffu)) & 0xffff0000u;
-    __builtin_amdgcn_raw_buffer_store_b16(uint16_t(((u & 0x80000000u) | mag) >> 16), r, vo, so,
-                                          POL);
+    uint32_t u = __float_as_uint(g) + (rnd & 0xffffu);
+    u = g != g ? 0x7fc00000u : u;
+    __builtin_amdgcn_raw_buffer_store_b16(uint16_t(u >> 16), r, vo, so, POL);
   }
 };
 
@@ -254,18 +248,19 @@ struct CFP16 {
     const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
     return float(__builtin_bit_cast(_Float16, h)) * (1.0f / kScale);
   }
-  // Stochastic rounding to FP16's 10-bit significand in its normal range
-  // [2^-14, 65504]: add 13 random bits below the kept ones to the float's
-  // magnitude and truncate, which leaves a value FP16 holds exactly.  Below
-  // the normal range (rare with the scale S) round to nearest even.
+  // Stochastic rounding to FP16's 10-bit significand: add 13 random bits
+  // below the kept ones to the scaled float's sign-magnitude word (a carry
+  // rounds the magnitude up, for either sign) and clear them.  In FP16's
+  // normal range [2^-14, 65504] the result is an FP16 value and the
+  // conversion exact; below it (deviations under 2^-26 with the scale) the
+  // conversion rounds once more to the nearest subnormal; above it the
+  // conversion overflows to infinity as round-to-nearest would.  A quiet
+  // NaN stays a NaN.
   template <int POL>
   __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*,
                             uint32_t rnd) {
-    const uint32_t u = __float_as_uint(g * kScale);
-    uint32_t mag = u & 0x7fffffffu;
-    if (mag >= 0x38800000u && mag < 0x477fe000u)
-      mag = (mag + (rnd & 0x1fffu)) & 0xffffe000u;
-    const _Float16 h = _Float16(__uint_as_float((u & 0x80000000u) | mag));
+    const uint32_t u = (__float_as_uint(g * kScale) + (rnd & 0x1fffu)) & 0xffffe000u;
+    const _Float16 h = _Float16(__uint_as_float(u));
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, h), r, vo, so, POL);
   }
 };
@@ -774,21 +769,27 @@ __device__ __forceinline__ void store(const typename C::R (&f)[L::Q], const Step
                                       uint32_t n) {
   const Rsrc fout = plane_set<L, C>(a.fout, a.plane);
   const uint32_t pb = uint32_t(a.plane) * C::B;
-  // counter for the stochastic rounding of the rounded formats: (node, q,
-  // step).  Formats that need at most 16 random bits take one 32-bit hash
-  // per pair of velocities (low half for even q, high half for odd q).
-  const uint32_t key =
-      C::kRandom ? mix32(a.step * 0x9e3779b9u + a.seed) ^ (n * uint32_t(L::Q)) : 0u;
-  uint32_t hpair = 0u;
+  // Random bits for the stochastic rounding of the rounded formats: a
+  // counter hash of (step, seed, node) seeds Marsaglia's xorshift32 (shift
+  // triple 13, 17, 5; never zero), stepped once per velocity, or once per
+  // pair of velocities (low half for even q, high half for odd q) where a
+  // format needs at most 16 bits.
+  uint32_t x = 0u;
+  if constexpr (C::kRandom)
+    x = mix32(mix32(a.step * 0x9e3779b9u + a.seed) ^ (n * uint32_t(L::Q))) | 1u;
+  auto next = [&x]() {
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
+  };
   auto body = [&](auto qc) {
     constexpr int q = decltype(qc)::value;
     uint32_t rnd = 0u;
-    if constexpr (C::kRandom && C::kRandBits <= 16) {
-      if constexpr (q % 2 == 0) hpair = mix32(key + uint32_t(q / 2) * 0x85ebca77u);
-      rnd = q % 2 == 0 ? hpair : hpair >> 16;
-    } else if constexpr (C::kRandom) {
-      rnd = mix32(key + uint32_t(q) * 0x85ebca77u);
-    }
+    if constexpr (C::kRandom && C::kRandBits <= 16)
+      rnd = q % 2 == 0 ? next() : x >> 16;
+    else if constexpr (C::kRandom)
+      rnd = next();
     C::template st<POL>(fout, n * C::B, uint32_t(q) * pb, f[q], a.tab, rnd);
   };
   static_for<0, L::Q>(body);
