@@ -686,9 +686,22 @@ __global__ __launch_bounds__(kBlock) void wall_kernel(StepArgs a) {
 // through ratio(wall, q)), Eq. (eq:dkboundary).  Returns deviations from w_q.
 // A wall with accommodation below one also reflects part of the incoming
 // mass specularly; wall_specular adds that share afterwards.
+// Copy of the two wall Maxwellians g^eq(u_w, T_w) (bottom in [0, Q), top in
+// [Q, 2Q)) in LDS, for the pulls of the rows next to a wall; by all threads
+// of the block, followed by a barrier.
+template <class L>
+__device__ __forceinline__ void stage_wall_tables(const StepArgs& a, double* wtab, int nthreads) {
+  for (int i = int(threadIdx.x); i < 2 * L::Q; i += nthreads)
+    wtab[i] = i < L::Q ? a.tab->gb[i] : a.tab->gt[i - L::Q];
+  __syncthreads();
+}
+
+// wtab: the wall Maxwellians staged by stage_wall_tables (read only in the
+// rows next to a wall).
 template <class L, class C, class Ratio>
 __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a, int y,
-                                     const int (&xw)[2 * max_ex<L>() + 1], Ratio&& ratio) {
+                                     const int (&xw)[2 * max_ex<L>() + 1], const double* wtab,
+                                     Ratio&& ratio) {
   using R = typename C::R;
   constexpr int NS = max_ex<L>();
   const Rsrc fin = plane_set<L, C>(a.fin, a.plane);
@@ -708,21 +721,31 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
     };
     static_for<0, L::Q>(body);
   } else {
-    auto body = [&](auto qc) {
+    // Rows next to a wall.  Every velocity's load is issued (a source
+    // beyond a wall reads this node's column in row y instead, inside the
+    // grid), then the sources beyond a wall take the re-emitted value
+    // f = g^eq(u_w, T_w) M / D: no branch separates the loads, so they are
+    // in flight together rather than one wait per velocity.
+    auto load = [&](auto qc) {
       constexpr int q = decltype(qc)::value;
       constexpr int ex = L::E[q][0], ey = L::E[q][1];
       const int ys = y - ey;
-      if (ey > 0 && ys < 0) {
-        // re-emitted by the bottom wall: f = g^eq(u_b, T_b) M / D
-        f[q] = R(a.tab->gb[q] * ratio(0, ex) - L::W[q]);
-      } else if (ey < 0 && ys >= a.ny) {
-        f[q] = R(a.tab->gt[q] * ratio(1, ex) - L::W[q]);  // top wall
-      } else {
-        f[q] = C::ld(fin, (uint32_t(ys) * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(q) * pb,
-                     a.tab);
+      const uint32_t row = uint32_t(ys < 0 || ys >= a.ny ? y : ys);
+      f[q] = C::ld(fin, (row * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(q) * pb, a.tab);
+    };
+    static_for<0, L::Q>(load);
+    auto emit = [&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int ex = L::E[q][0], ey = L::E[q][1];
+      if constexpr (ey > 0) {  // bottom wall (y - e_y < 0)
+        const R v = R(wtab[q] * ratio(0, ex) - L::W[q]);
+        f[q] = y - ey < 0 ? v : f[q];
+      } else if constexpr (ey < 0) {  // top wall (y - e_y >= ny)
+        const R v = R(wtab[L::Q + q] * ratio(1, ex) - L::W[q]);
+        f[q] = y - ey >= a.ny ? v : f[q];
       }
     };
-    static_for<0, L::Q>(body);
+    static_for<0, L::Q>(emit);
   }
 }
 
@@ -822,15 +845,22 @@ template <class L, class C, bool MOM, bool FORCE>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
   using R = typename C::R;
   constexpr int NS = max_ex<L>();
+  __shared__ double wtab_s[2 * L::Q];
   const long long nodes = (long long)a.nx * a.ny;
-  const long long n = (long long)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const long long base = (long long)xcd_remap(blockIdx.x, gridDim.x) * kBlock;
+  // blocks holding a row next to a wall stage the wall Maxwellians
+  // (block-uniform test, before any thread leaves)
+  const long long last = (base + kBlock < nodes ? base + kBlock : nodes) - 1;
+  if (base / a.nx < L::N || last / a.nx >= a.ny - L::N)
+    stage_wall_tables<L>(a, wtab_s, kBlock);
+  const long long n = base + threadIdx.x;
   if (n >= nodes) return;
   const int y = int(n / a.nx);
   const int x = int(n - (long long)y * a.nx);
   int xw[2 * NS + 1];
   wrapped_columns<NS, false>(x, a.nx, xw);
   R f[L::Q];
-  pull<L, C>(f, a, y, xw,
+  pull<L, C>(f, a, y, xw, wtab_s,
              [&](int wall, int ex) { return a.ratio[wall * a.nx + xw[ex + NS]]; });
   wall_specular<L, C>(f, a, y, xw);
   relax<L, R, MOM, FORCE>(f, a, a.mom, nodes, n);
@@ -848,6 +878,7 @@ __global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
   using R = typename C::R;
   constexpr int NS = max_ex<L>();
   __shared__ double ratio_s[kBlock + 2 * NS];
+  __shared__ double wtab_s[2 * L::Q];
   const int bpr = a.nx / kBlock;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int r = b / bpr;
@@ -873,10 +904,10 @@ __global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
       ratio_s[s] = top ? (a.tab->Wt + ghost_column_deviation<L, C, true>(a, c)) / a.tab->Dt
                        : (a.tab->Wb + ghost_column_deviation<L, C, false>(a, c)) / a.tab->Db;
     }
-    __syncthreads();
+    stage_wall_tables<L>(a, wtab_s, kBlock);  // ends with the barrier
   }
   R f[L::Q];
-  pull<L, C>(f, a, y, xw,
+  pull<L, C>(f, a, y, xw, wtab_s,
              [&](int, int ex) { return ratio_s[int(threadIdx.x) - ex + NS]; });
   if (bottom || top) wall_specular<L, C>(f, a, y, xw);
   const long long nodes = (long long)a.nx * a.ny;
@@ -966,7 +997,8 @@ __device__ __forceinline__ void residual_terms(const double* mom, double* snap, 
 // output fields; its own loop, so that the populations of the two variants
 // never share live ranges (one loop with both would hold more registers).
 template <class L, class C, bool FORCE, bool MOM>
-__device__ __forceinline__ void case_nodes(const StepArgs& a, int nodes, const double* ratio_s) {
+__device__ __forceinline__ void case_nodes(const StepArgs& a, int nodes, const double* ratio_s,
+                                           const double* wtab_s) {
   using R = typename C::R;
   constexpr int NS = max_ex<L>();
   for (int n = threadIdx.x; n < nodes; n += kBatchBlock) {
@@ -975,7 +1007,7 @@ __device__ __forceinline__ void case_nodes(const StepArgs& a, int nodes, const d
     int xw[2 * NS + 1];
     wrapped_columns<NS, false>(x, a.nx, xw);
     R f[L::Q];
-    pull<L, C>(f, a, y, xw,
+    pull<L, C>(f, a, y, xw, wtab_s,
                [&](int wall, int ex) { return ratio_s[wall * a.nx + xw[ex + NS]]; });
     wall_specular<L, C>(f, a, y, xw);
     relax<L, R, MOM, FORCE>(f, a, a.mom, nodes, n);
@@ -985,8 +1017,9 @@ __device__ __forceinline__ void case_nodes(const StepArgs& a, int nodes, const d
 
 template <class L, class C, bool FORCE>
 __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, double* ratio_s,
-                                         double (*red)[kBatchBlock]) {
+                                         double (*red)[kBatchBlock], double* wtab_s) {
   StepArgs a = cd.a;
+  stage_wall_tables<L>(a, wtab_s, kBatchBlock);
   const int nodes = a.nx * a.ny;
   const int lane = int(threadIdx.x & 63);
   const int wave = int(threadIdx.x >> 6);
@@ -1011,9 +1044,9 @@ __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, doubl
       }
       __syncthreads();
       if (s == W - 1)
-        case_nodes<L, C, FORCE, true>(a, nodes, ratio_s);
+        case_nodes<L, C, FORCE, true>(a, nodes, ratio_s, wtab_s);
       else
-        case_nodes<L, C, FORCE, false>(a, nodes, ratio_s);
+        case_nodes<L, C, FORCE, false>(a, nodes, ratio_s, wtab_s);
       __syncthreads();
       cur ^= 1;
     }
@@ -1055,14 +1088,15 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(const CaseDesc* __re
                                                             CaseOut* out) {
   __shared__ double ratio_s[2 * kBatchMaxNx];
   __shared__ double red[4][kBatchBlock];
+  __shared__ double wtab_s[2 * kQMax];
   const CaseDesc& cd = cases[blockIdx.x];
   const int lat = cd.lattice;
   if (lat == 0 && (SETS & 1)) {
-    if constexpr ((SETS & 1) != 0) run_case<D2Q16, C, FORCE>(cd, out, ratio_s, red);
+    if constexpr ((SETS & 1) != 0) run_case<D2Q16, C, FORCE>(cd, out, ratio_s, red, wtab_s);
   } else if (lat == 1 && (SETS & 2)) {
-    if constexpr ((SETS & 2) != 0) run_case<D2Q17, C, FORCE>(cd, out, ratio_s, red);
+    if constexpr ((SETS & 2) != 0) run_case<D2Q17, C, FORCE>(cd, out, ratio_s, red, wtab_s);
   } else if (lat == 2 && (SETS & 4)) {
-    if constexpr ((SETS & 4) != 0) run_case<D3Q121, C, FORCE>(cd, out, ratio_s, red);
+    if constexpr ((SETS & 4) != 0) run_case<D3Q121, C, FORCE>(cd, out, ratio_s, red, wtab_s);
   } else if (threadIdx.x == 0) {
     out[blockIdx.x].residual = __builtin_nan("");
     out[blockIdx.x].mass = __builtin_nan("");
