@@ -87,6 +87,29 @@ constexpr int opposite(int q) {
       return p;
   return -1;
 }
+// Velocity subsets for a node split over P groups of lanes: the pairs
+// {c, -c} in the order of their lower index are dealt round-robin to the
+// parts, the rest velocity to part 0.  PART = -1 is the whole set.
+template <class L>
+constexpr int pair_rank(int q) {
+  const int o = opposite<L>(q);
+  if (o == q) return -1;
+  const int lo = q < o ? q : o;
+  int r = 0;
+  for (int p = 0; p < lo; ++p)
+    if (opposite<L>(p) > p) ++r;
+  return r;
+}
+template <class L, int PART, int P>
+constexpr bool in_part(int q) {
+  if constexpr (PART < 0) {
+    return true;
+  } else {
+    const int r = pair_rank<L>(q);
+    return (r < 0 ? 0 : r % P) == PART;
+  }
+}
+
 template <class L>
 constexpr int first_nonzero(int k) {
   for (int p = 0; p < L::Q; ++p) {
@@ -410,21 +433,44 @@ struct Macro {
 // (sum w c = 0), and for the thermal set rho D T = D + sum g |c|^2 - rho u^2
 // (sum w |c|^2 = D); theta = T - 1.  Isothermal sets use T = 1.
 // A is the arithmetic type, G the type the deviations are held in.
-template <class L, class R, class G = R>
-__device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
+template <class R>
+struct Sums {
+  R drho, mx, my, mz, e2;  // sum g, sum g e, sum g |e|^2
+};
+
+// The sums of Eq. (eq:summac) over the deviations of velocity subset PART
+// (of P); the whole set for PART = -1.
+template <class L, class R, class G = R, int PART = -1, int P = 1>
+__device__ __forceinline__ Sums<R> sums(const G (&g)[L::Q]) {
   R drho = 0, mx = 0, my = 0, mz = 0, e2 = 0;
   auto body = [&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
-    const R v = R(g[q]);
-    drho = q == 0 ? v : drho + v;
-    mx = accum<ex, q == first_nonzero<L>(0)>(mx, v);
-    my = accum<ey, q == first_nonzero<L>(1)>(my, v);
-    mz = accum<ez, q == first_nonzero<L>(2)>(mz, v);
-    if constexpr (L::THERMAL)
-      e2 = accum<ex * ex + ey * ey + ez * ez, q == first_nonzero<L>(3)>(e2, v);
+    if constexpr (in_part<L, PART, P>(q)) {
+      const R v = R(g[q]);
+      if constexpr (PART < 0) {
+        drho = q == 0 ? v : drho + v;
+        mx = accum<ex, q == first_nonzero<L>(0)>(mx, v);
+        my = accum<ey, q == first_nonzero<L>(1)>(my, v);
+        mz = accum<ez, q == first_nonzero<L>(2)>(mz, v);
+        if constexpr (L::THERMAL)
+          e2 = accum<ex * ex + ey * ey + ez * ez, q == first_nonzero<L>(3)>(e2, v);
+      } else {
+        drho += v;
+        mx = add_scaled<ex>(mx, v);
+        my = add_scaled<ey>(my, v);
+        mz = add_scaled<ez>(mz, v);
+        if constexpr (L::THERMAL) e2 = add_scaled<ex * ex + ey * ey + ez * ez>(e2, v);
+      }
+    }
   };
   static_for<0, L::Q>(body);
+  return Sums<R>{drho, mx, my, mz, e2};
+}
+
+template <class L, class R>
+__device__ __forceinline__ Macro<R> macro_from(const Sums<R>& t) {
+  const R drho = t.drho, mx = t.mx, my = t.my, mz = t.mz, e2 = t.e2;
   Macro<R> m;
   m.drho = drho;
   m.rho = R(1) + drho;
@@ -440,6 +486,11 @@ __device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
     m.th = R(0);
   }
   return m;
+}
+
+template <class L, class R, class G = R>
+__device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
+  return macro_from<L, R>(sums<L, R, G>(g));
 }
 
 // g* = g - omega (g - (f^eq - w)), in place.  With MOM, also writes the
@@ -459,10 +510,18 @@ __device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
 // F = a . d f^eq / du; the trapezoidal change of variable of Sec. II applied
 // to collision + force gives g* = g + omega (f^eq - w - g) + tau/(tau+1/2) F
 // with f^eq and F at the moments of f: u = u[f~] + a/2, T = T[f~] + a^2/(4D).
-template <class L, class R, bool MOM = false, bool FORCE = false>
-__device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* mom = nullptr,
-                                      long long nodes = 0, long long n = 0) {
-  Macro<R> m = macro<L, R>(g);
+template <class R>
+struct NeqSums {
+  R sxy, qx, qy, qz;  // non-equilibrium sums of the stress and heat flux
+};
+
+// The collision of velocity subset PART (of P; all for PART = -1) given the
+// node's moments m of f~ (turned into those of f under a force).  With MOM,
+// also accumulates the subset's stress and heat-flux sums into ns.  Returns
+// tau/(tau+1/2) of the node.
+template <class L, class R, bool MOM, bool FORCE, int PART = -1, int P = 1>
+__device__ __forceinline__ R relax_part(R (&g)[L::Q], const StepArgs& a, Macro<R>& m,
+                                        NeqSums<R>& ns) {
   R fax = 0, fay = 0, faz = 0;
   if constexpr (FORCE) {
     // moments of f from those of f~: u + a/2, T + a^2/(4D)
@@ -525,7 +584,9 @@ __device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* m
     constexpr int o = opposite<L>(q);
     static_assert(o >= 0, "velocity set not closed under c -> -c");
     constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
-    if constexpr (o == q) {
+    if constexpr (!in_part<L, PART, P>(q)) {
+      // another part's velocity
+    } else if constexpr (o == q) {
       finish(qc, R(0), R(L::W[q]) * k.poly0());
     } else if constexpr (q < o) {
       const R x = dot_e<ex, ey, ez>(sx, sy, sz);
@@ -536,7 +597,17 @@ __device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* m
     }
   };
   static_for<0, L::Q>(body);
-  if constexpr (MOM) {
+  ns = NeqSums<R>{sxy, qx, qy, qz};
+  return kf;
+}
+
+// The output fields of node n from its moments, tau/(tau+1/2) and the
+// non-equilibrium sums.
+template <class L, class R>
+__device__ __forceinline__ void write_fields(double* mom, long long nodes, long long n,
+                                             const Macro<R>& m, R kf, const NeqSums<R>& ns) {
+  const R sxy = ns.sxy, qx = ns.qx, qy = ns.qy, qz = ns.qz;
+  {
     mom[0 * nodes + n] = 1.0 + double(m.drho);
     mom[1 * nodes + n] = double(m.ux);
     mom[2 * nodes + n] = double(m.uy);
@@ -548,12 +619,23 @@ __device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* m
       mom[7 * nodes + n] = 0.5 * double(kf * qy);
       mom[8 * nodes + n] = 0.5 * double(kf * qz);
     } else {
+      const R uu =
+          L::D == 3 ? m.ux * m.ux + m.uy * m.uy + m.uz * m.uz : m.ux * m.ux + m.uy * m.uy;
       const R rest = -(R(L::D + 2) + uu);
       mom[6 * nodes + n] = 0.5 * double(m.ux * rest + qx);
       mom[7 * nodes + n] = 0.5 * double(m.uy * rest + qy);
       mom[8 * nodes + n] = 0.5 * double(m.uz * rest + qz);
     }
   }
+}
+
+template <class L, class R, bool MOM = false, bool FORCE = false>
+__device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* mom = nullptr,
+                                      long long nodes = 0, long long n = 0) {
+  Macro<R> m = macro<L, R>(g);
+  NeqSums<R> ns;
+  const R kf = relax_part<L, R, MOM, FORCE>(g, a, m, ns);
+  if constexpr (MOM) write_fields<L, R>(mom, nodes, n, m, kf, ns);
 }
 
 // Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8,
@@ -697,8 +779,9 @@ __device__ __forceinline__ void stage_wall_tables(const StepArgs& a, double* wta
 }
 
 // wtab: the wall Maxwellians staged by stage_wall_tables (read only in the
-// rows next to a wall).
-template <class L, class C, class Ratio>
+// rows next to a wall).  PART / P: only the velocities of that subset.
+// UNIFORM_Y: y is the same for the whole workgroup (the row-tiled update).
+template <class L, class C, int PART = -1, int P = 1, bool UNIFORM_Y = false, class Ratio>
 __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a, int y,
                                      const int (&xw)[2 * max_ex<L>() + 1], const double* wtab,
                                      Ratio&& ratio) {
@@ -717,18 +800,39 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
     auto body = [&](auto qc) {
       constexpr int q = decltype(qc)::value;
       constexpr int ex = L::E[q][0], ey = L::E[q][1];
-      f[q] = C::ld(fin, vo[ex + NS], uint32_t(q) * pb + uint32_t(L::N - ey) * rb, a.tab);
+      if constexpr (in_part<L, PART, P>(q))
+        f[q] = C::ld(fin, vo[ex + NS], uint32_t(q) * pb + uint32_t(L::N - ey) * rb, a.tab);
+    };
+    static_for<0, L::Q>(body);
+  } else if constexpr (UNIFORM_Y) {
+    // A row next to a wall, the same for the whole workgroup: which sources
+    // lie beyond a wall is uniform, so the per-velocity choice is a scalar
+    // branch; a source beyond the wall takes the re-emitted value
+    // f = g^eq(u_w, T_w) M / D (wall table and ratios in LDS).
+    auto body = [&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int ex = L::E[q][0], ey = L::E[q][1];
+      if constexpr (!in_part<L, PART, P>(q)) return;
+      const int ys = y - ey;
+      if (ey > 0 && ys < 0)
+        f[q] = R(wtab[q] * ratio(0, ex) - L::W[q]);
+      else if (ey < 0 && ys >= a.ny)
+        f[q] = R(wtab[L::Q + q] * ratio(1, ex) - L::W[q]);
+      else
+        f[q] = C::ld(fin, (uint32_t(ys) * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(q) * pb,
+                     a.tab);
     };
     static_for<0, L::Q>(body);
   } else {
-    // Rows next to a wall.  Every velocity's load is issued (a source
-    // beyond a wall reads this node's column in row y instead, inside the
-    // grid), then the sources beyond a wall take the re-emitted value
-    // f = g^eq(u_w, T_w) M / D: no branch separates the loads, so they are
-    // in flight together rather than one wait per velocity.
+    // Rows next to a wall, y varying across the wave.  Every velocity's
+    // load is issued (a source beyond a wall reads this node's column in
+    // row y instead, inside the grid), then the sources beyond a wall take
+    // the re-emitted value: no divergent branch separates the loads, so
+    // they are in flight together rather than one wait per velocity.
     auto load = [&](auto qc) {
       constexpr int q = decltype(qc)::value;
       constexpr int ex = L::E[q][0], ey = L::E[q][1];
+      if constexpr (!in_part<L, PART, P>(q)) return;
       const int ys = y - ey;
       const uint32_t row = uint32_t(ys < 0 || ys >= a.ny ? y : ys);
       f[q] = C::ld(fin, (row * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(q) * pb, a.tab);
@@ -737,7 +841,9 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
     auto emit = [&](auto qc) {
       constexpr int q = decltype(qc)::value;
       constexpr int ex = L::E[q][0], ey = L::E[q][1];
-      if constexpr (ey > 0) {  // bottom wall (y - e_y < 0)
+      if constexpr (!in_part<L, PART, P>(q)) {
+        // another part's velocity
+      } else if constexpr (ey > 0) {  // bottom wall (y - e_y < 0)
         const R v = R(wtab[q] * ratio(0, ex) - L::W[q]);
         f[q] = y - ey < 0 ? v : f[q];
       } else if constexpr (ey < 0) {  // top wall (y - e_y >= ny)
@@ -756,7 +862,7 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
 // e_y reversed and y' the source row reflected at the wall plane (-1 - y_s
 // below the bottom wall, 2 ny - 1 - y_s above the top one).  Does nothing
 // away from the walls or for a = 1 (the paper's diffuse wall).
-template <class L, class C>
+template <class L, class C, int PART = -1, int P = 1>
 __device__ __forceinline__ void wall_specular(typename C::R (&f)[L::Q], const StepArgs& a, int y,
                                               const int (&xw)[2 * max_ex<L>() + 1]) {
   using R = typename C::R;
@@ -772,6 +878,7 @@ __device__ __forceinline__ void wall_specular(typename C::R (&f)[L::Q], const St
     constexpr int ex = L::E[q][0], ey = L::E[q][1];
     constexpr int m = mirror_y<L>(q);
     static_assert(m >= 0, "velocity set not symmetric under y reversal");
+    if constexpr (!in_part<L, PART, P>(q)) return;
     const int ys = y - ey;
     if (ey > 0 && ys < 0 && bottom) {
       const double gs = double(C::ld(fin, (uint32_t(-1 - ys) * nx + uint32_t(xw[ex + NS])) * C::B,
@@ -787,9 +894,11 @@ __device__ __forceinline__ void wall_specular(typename C::R (&f)[L::Q], const St
   static_for<0, L::Q>(body);
 }
 
-template <class L, class C, int POL = kStoreNT>
+template <class L, class C, int POL = kStoreNT, int PART = -1, int P = 1>
 __device__ __forceinline__ void store(const typename C::R (&f)[L::Q], const StepArgs& a,
                                       uint32_t n) {
+  // a subset's stores would not draw the same rounding bits as the whole set's
+  static_assert(PART < 0 || !C::kRandom, "velocity subsets only for formats without rounding");
   const Rsrc fout = plane_set<L, C>(a.fout, a.plane);
   const uint32_t pb = uint32_t(a.plane) * C::B;
   // Random bits for the stochastic rounding of the rounded formats: a
@@ -813,7 +922,8 @@ __device__ __forceinline__ void store(const typename C::R (&f)[L::Q], const Step
       rnd = q % 2 == 0 ? next() : x >> 16;
     else if constexpr (C::kRandom)
       rnd = next();
-    C::template st<POL>(fout, n * C::B, uint32_t(q) * pb, f[q], a.tab, rnd);
+    if constexpr (in_part<L, PART, P>(q))
+      C::template st<POL>(fout, n * C::B, uint32_t(q) * pb, f[q], a.tab, rnd);
   };
   static_for<0, L::Q>(body);
 }
@@ -907,8 +1017,14 @@ __global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
     stage_wall_tables<L>(a, wtab_s, kBlock);  // ends with the barrier
   }
   R f[L::Q];
-  pull<L, C>(f, a, y, xw, wtab_s,
-             [&](int, int ex) { return ratio_s[int(threadIdx.x) - ex + NS]; });
+  // Wall rows: the formats that schedule them first (their wall blocks run
+  // beside interior ones) take the branchless pull, which keeps every load
+  // in flight (D3Q121 1024^2: FP32 storage 257 -> 233 us, 16-bit 127 -> 123
+  // us per step); FP32 and FP64, whose wall blocks end the grid, take the
+  // uniform branches, which skip the loads of sources beyond the wall (the
+  // branchless pull cost D2Q17 2048^2 FP32 0.65 us per step).
+  pull<L, C, -1, 1, !C::kWallRowsFirst>(
+      f, a, y, xw, wtab_s, [&](int, int ex) { return ratio_s[int(threadIdx.x) - ex + NS]; });
   if (bottom || top) wall_specular<L, C>(f, a, y, xw);
   const long long nodes = (long long)a.nx * a.ny;
   const uint32_t n = uint32_t(y) * uint32_t(a.nx) + uint32_t(x);
@@ -996,12 +1112,12 @@ __device__ __forceinline__ void residual_terms(const double* mom, double* snap, 
 // already in LDS).  MOM: the last step of a window, which also writes the
 // output fields; its own loop, so that the populations of the two variants
 // never share live ranges (one loop with both would hold more registers).
-template <class L, class C, bool FORCE, bool MOM>
+template <class L, class C, bool FORCE, bool MOM, int NT>
 __device__ __forceinline__ void case_nodes(const StepArgs& a, int nodes, const double* ratio_s,
                                            const double* wtab_s) {
   using R = typename C::R;
   constexpr int NS = max_ex<L>();
-  for (int n = threadIdx.x; n < nodes; n += kBatchBlock) {
+  for (int n = threadIdx.x; n < nodes; n += NT) {
     const int y = n / a.nx;
     const int x = n - y * a.nx;
     int xw[2 * NS + 1];
@@ -1015,15 +1131,132 @@ __device__ __forceinline__ void case_nodes(const StepArgs& a, int nodes, const d
   }
 }
 
+// Threads per case of the batched kernel, and the number of velocity
+// subsets a node of set L is split over.  A case runs on one workgroup and
+// is latency-bound: the FP32 instance without a body force gives each case
+// 1024 threads and splits its D3Q121 nodes over four groups of four waves
+// (about 30 velocities per lane instead of 121).  The force variant (whose
+// D3Q121 path spills at 128 or 256 registers per lane when split) and the
+// other formats keep 256 threads and whole nodes.
+template <class C, bool FORCE>
+constexpr int batch_threads() {
+  return std::is_same<C, CF32>::value && !FORCE ? 1024 : kBatchBlock;
+}
 template <class L, class C, bool FORCE>
+constexpr int batch_parts() {
+  return std::is_same<C, CF32>::value && !FORCE && L::Q > 100 ? 4 : 1;
+}
+
+// One step of one case's nodes with each node split over P groups of
+// NT / P threads (group PART, a compile-time velocity subset; the group
+// index is uniform over each wave).  Each group pulls its velocities and
+// puts its partial sums of Eq. (eq:summac) in LDS; after a barrier every
+// group adds the P partial sums in the same fixed order, forms the moments
+// and relaxes and stores its own velocities.  With MOM the stress and heat
+// flux sums are combined the same way and group 0 writes the fields.  All
+// groups pass the same barriers.  part_s: (5 + 4) x NT values of R.
+template <class L, class C, bool FORCE, bool MOM, int NT, int P, int PART>
+__device__ __forceinline__ void case_nodes_part(const StepArgs& a, int nodes,
+                                                const double* ratio_s, const double* wtab_s,
+                                                typename C::R* part_s) {
+  using R = typename C::R;
+  constexpr int NS = max_ex<L>();
+  constexpr int kSlots = NT / P;
+  R* psum = part_s;             // [P][5][kSlots]
+  R* pneq = part_s + 5 * NT;    // [P][4][kSlots]
+  const int slot = int(threadIdx.x) - PART * kSlots;
+  for (int base = 0; base < nodes; base += kSlots) {
+    const int n = base + slot;
+    const bool active = n < nodes;
+    R f[L::Q];
+    Sums<R> t{R(0), R(0), R(0), R(0), R(0)};
+    if (active) {
+      const int y = n / a.nx;
+      const int x = n - y * a.nx;
+      int xw[2 * NS + 1];
+      wrapped_columns<NS, false>(x, a.nx, xw);
+      pull<L, C, PART, P>(f, a, y, xw, wtab_s, [&](int wall, int ex) {
+        return ratio_s[wall * a.nx + xw[ex + NS]];
+      });
+      wall_specular<L, C, PART, P>(f, a, y, xw);
+      t = sums<L, R, R, PART, P>(f);
+    }
+    psum[(PART * 5 + 0) * kSlots + slot] = t.drho;
+    psum[(PART * 5 + 1) * kSlots + slot] = t.mx;
+    psum[(PART * 5 + 2) * kSlots + slot] = t.my;
+    psum[(PART * 5 + 3) * kSlots + slot] = t.mz;
+    psum[(PART * 5 + 4) * kSlots + slot] = t.e2;
+    __syncthreads();
+    Macro<R> m{};
+    R kf = R(0);
+    if (active) {
+      R v[5];
+      for (int k = 0; k < 5; ++k) {
+        v[k] = psum[k * kSlots + slot];
+        for (int p = 1; p < P; ++p) v[k] += psum[(p * 5 + k) * kSlots + slot];
+      }
+      m = macro_from<L, R>(Sums<R>{v[0], v[1], v[2], v[3], v[4]});
+      NeqSums<R> ns;
+      kf = relax_part<L, R, MOM, FORCE, PART, P>(f, a, m, ns);
+      store<L, C, kStoreCached, PART, P>(f, a, uint32_t(n));
+      if constexpr (MOM) {
+        pneq[(PART * 4 + 0) * kSlots + slot] = ns.sxy;
+        pneq[(PART * 4 + 1) * kSlots + slot] = ns.qx;
+        pneq[(PART * 4 + 2) * kSlots + slot] = ns.qy;
+        pneq[(PART * 4 + 3) * kSlots + slot] = ns.qz;
+      }
+    }
+    if constexpr (MOM) {
+      __syncthreads();
+      if (PART == 0 && active) {
+        R w[4];
+        for (int k = 0; k < 4; ++k) {
+          w[k] = pneq[k * kSlots + slot];
+          for (int p = 1; p < P; ++p) w[k] += pneq[(p * 4 + k) * kSlots + slot];
+        }
+        write_fields<L, R>(a.mom, nodes, n, m, kf, NeqSums<R>{w[0], w[1], w[2], w[3]});
+      }
+    }
+    __syncthreads();  // the partial sums are reused by the next pass
+  }
+}
+
+// One step of the nodes: whole nodes per thread, or split (see above).
+template <class L, class C, bool FORCE, bool MOM, int NT>
+__device__ __forceinline__ void case_step(const StepArgs& a, int nodes, const double* ratio_s,
+                                          const double* wtab_s, typename C::R* part_s) {
+  constexpr int P = batch_parts<L, C, FORCE>();
+  if constexpr (P == 1) {
+    case_nodes<L, C, FORCE, MOM, NT>(a, nodes, ratio_s, wtab_s);
+  } else if constexpr (P == 2) {
+    static_assert(NT % (64 * P) == 0, "groups of whole waves");
+    const int part = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / (NT / P));
+    if (part == 0)
+      case_nodes_part<L, C, FORCE, MOM, NT, P, 0>(a, nodes, ratio_s, wtab_s, part_s);
+    else
+      case_nodes_part<L, C, FORCE, MOM, NT, P, 1>(a, nodes, ratio_s, wtab_s, part_s);
+  } else {
+    static_assert(P == 4 && NT % (64 * P) == 0, "four groups of whole waves");
+    const int part = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / (NT / P));
+    switch (part) {
+      case 0: case_nodes_part<L, C, FORCE, MOM, NT, P, 0>(a, nodes, ratio_s, wtab_s, part_s); break;
+      case 1: case_nodes_part<L, C, FORCE, MOM, NT, P, 1>(a, nodes, ratio_s, wtab_s, part_s); break;
+      case 2: case_nodes_part<L, C, FORCE, MOM, NT, P, 2>(a, nodes, ratio_s, wtab_s, part_s); break;
+      default: case_nodes_part<L, C, FORCE, MOM, NT, P, 3>(a, nodes, ratio_s, wtab_s, part_s); break;
+    }
+  }
+}
+
+template <class L, class C, bool FORCE, int NT>
 __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, double* ratio_s,
-                                         double (*red)[kBatchBlock], double* wtab_s) {
+                                         double (*red)[NT], double* wtab_s,
+                                         typename C::R* part_s) {
   StepArgs a = cd.a;
-  stage_wall_tables<L>(a, wtab_s, kBatchBlock);
+  stage_wall_tables<L>(a, wtab_s, NT);
   const int nodes = a.nx * a.ny;
   const int lane = int(threadIdx.x & 63);
   const int wave = int(threadIdx.x >> 6);
-  constexpr int kWaves = kBatchBlock / 64;
+  constexpr int kWaves = NT / 64;
   const int W = cd.window;
   int cur = cd.cur;
   int done = 0;
@@ -1044,16 +1277,16 @@ __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, doubl
       }
       __syncthreads();
       if (s == W - 1)
-        case_nodes<L, C, FORCE, true>(a, nodes, ratio_s, wtab_s);
+        case_step<L, C, FORCE, true, NT>(a, nodes, ratio_s, wtab_s, part_s);
       else
-        case_nodes<L, C, FORCE, false>(a, nodes, ratio_s, wtab_s);
+        case_step<L, C, FORCE, false, NT>(a, nodes, ratio_s, wtab_s, part_s);
       __syncthreads();
       cur ^= 1;
     }
     done += W;
     double v[4] = {0, 0, 0, 0};
-    for (int i = threadIdx.x; i < nodes; i += kBatchBlock) residual_terms(a.mom, cd.snap, nodes, i, v);
-    block_sum4<kBatchBlock>(v, red);
+    for (int i = threadIdx.x; i < nodes; i += NT) residual_terms(a.mom, cd.snap, nodes, i, v);
+    block_sum4<NT>(v, red);
     if (threadIdx.x == 0)
       for (int k = 0; k < 4; ++k) cd.result[k] = v[k];
     const double ru = sqrt(v[1]) / (double(W) * cd.uref * sqrt(double(nodes)));
@@ -1084,19 +1317,23 @@ __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, doubl
 // (in one instance with the others its FP64 path spills to scratch and slows
 // every case).  A case of a set the instance does not carry reports failure.
 template <class C, bool FORCE, int SETS>
-__global__ __launch_bounds__(kBatchBlock) void batch_kernel(const CaseDesc* __restrict__ cases,
-                                                            CaseOut* out) {
+__global__ __launch_bounds__((batch_threads<C, FORCE>())) void batch_kernel(
+    const CaseDesc* __restrict__ cases, CaseOut* out) {
+  constexpr int NT = batch_threads<C, FORCE>();
+  // LDS of the split node loop (D3Q121 in the instances that split it)
+  constexpr int kPartLds = (SETS & 4) != 0 && batch_parts<D3Q121, C, FORCE>() > 1 ? 9 * NT : 1;
   __shared__ double ratio_s[2 * kBatchMaxNx];
-  __shared__ double red[4][kBatchBlock];
+  __shared__ double red[4][NT];
   __shared__ double wtab_s[2 * kQMax];
+  __shared__ typename C::R part_s[kPartLds];
   const CaseDesc& cd = cases[blockIdx.x];
   const int lat = cd.lattice;
   if (lat == 0 && (SETS & 1)) {
-    if constexpr ((SETS & 1) != 0) run_case<D2Q16, C, FORCE>(cd, out, ratio_s, red, wtab_s);
+    if constexpr ((SETS & 1) != 0) run_case<D2Q16, C, FORCE, NT>(cd, out, ratio_s, red, wtab_s, part_s);
   } else if (lat == 1 && (SETS & 2)) {
-    if constexpr ((SETS & 2) != 0) run_case<D2Q17, C, FORCE>(cd, out, ratio_s, red, wtab_s);
+    if constexpr ((SETS & 2) != 0) run_case<D2Q17, C, FORCE, NT>(cd, out, ratio_s, red, wtab_s, part_s);
   } else if (lat == 2 && (SETS & 4)) {
-    if constexpr ((SETS & 4) != 0) run_case<D3Q121, C, FORCE>(cd, out, ratio_s, red, wtab_s);
+    if constexpr ((SETS & 4) != 0) run_case<D3Q121, C, FORCE, NT>(cd, out, ratio_s, red, wtab_s, part_s);
   } else if (threadIdx.x == 0) {
     out[blockIdx.x].residual = __builtin_nan("");
     out[blockIdx.x].mass = __builtin_nan("");
@@ -1173,8 +1410,8 @@ hipError_t batch_launch(const CaseDesc* cases, int ncase, CaseOut* out, hipStrea
 template <class C, bool FORCE, int SETS>
 hipError_t batch_launch(const CaseDesc* cases, int ncase, CaseOut* out, hipStream_t s) {
   clear_stale_error();
-  hipLaunchKernelGGL((batch_kernel<C, FORCE, SETS>), dim3(unsigned(ncase)), dim3(kBatchBlock), 0,
-                     s, cases, out);
+  hipLaunchKernelGGL((batch_kernel<C, FORCE, SETS>), dim3(unsigned(ncase)),
+                     dim3(batch_threads<C, FORCE>()), 0, s, cases, out);
   return hipGetLastError();
 }
 #endif
