@@ -719,25 +719,27 @@ struct WallTerms {
   }
 };
 
+// Pooled incoming mass of ghost column xp (deviations only), the same in
+// every lane: the wave issues every term's load at the same (wave-uniform)
+// address, with no branch between them, and adds the terms in their fixed
+// order.  (A version that gave each lane its own terms behind a per-term
+// branch waited for each load in turn: 88 memory latencies per wall and
+// step on D3Q121.)
 template <class L, class C, bool TOP>
-__device__ __forceinline__ double ghost_mass(Rsrc fin, const StepArgs& a, int xp, int lane) {
+__device__ __forceinline__ double ghost_mass(Rsrc fin, const StepArgs& a, int xp) {
   using W = WallTerms<L>;
   double acc = 0.0;
   auto body = [&](auto tc) {
     constexpr int t = decltype(tc)::value;
     constexpr auto T = TOP ? W::top().t[t] : W::bottom().t[t];
-    if (lane == (t & 63)) {
-      int xs = xp - T.ex;
-      while (xs < 0) xs += a.nx;
-      while (xs >= a.nx) xs -= a.nx;
-      const int row = TOP ? a.ny - 1 - T.j : T.j;
-      acc += double(C::ld(fin, (uint32_t(row) * uint32_t(a.nx) + uint32_t(xs)) * C::B,
-                          uint32_t(T.q) * uint32_t(a.plane) * C::B, a.tab));
-    }
+    int xs = xp - T.ex;
+    while (xs < 0) xs += a.nx;
+    while (xs >= a.nx) xs -= a.nx;
+    const int row = TOP ? a.ny - 1 - T.j : T.j;
+    acc += double(C::ld(fin, (uint32_t(row) * uint32_t(a.nx) + uint32_t(xs)) * C::B,
+                        uint32_t(T.q) * uint32_t(a.plane) * C::B, a.tab));
   };
   static_for<0, W::NT>(body);
-  // butterfly over the 64 lanes: fixed order, every lane ends with the sum
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   return acc;
 }
 
@@ -751,9 +753,9 @@ __global__ __launch_bounds__(kBlock) void wall_kernel(StepArgs a) {
   const int xp = top ? wave - a.nx : wave;
   double M;
   if (top)
-    M = ghost_mass<L, C, true>(fin, a, xp, lane);
+    M = ghost_mass<L, C, true>(fin, a, xp);
   else
-    M = ghost_mass<L, C, false>(fin, a, xp, lane);
+    M = ghost_mass<L, C, false>(fin, a, xp);
   // pooled incoming mass = rest-state part + deviations; ratio of
   // Eq. (eq:dkboundary) numerator to its denominator
   if (lane == 0)
@@ -1270,8 +1272,8 @@ __device__ __forceinline__ void run_case(const CaseDesc& cd, CaseOut* out, doubl
       for (int p = wave; p < 2 * a.nx; p += kWaves) {
         const bool top = p >= a.nx;
         const int xp = top ? p - a.nx : p;
-        const double M = top ? ghost_mass<L, C, true>(fin, a, xp, lane)
-                             : ghost_mass<L, C, false>(fin, a, xp, lane);
+        const double M = top ? ghost_mass<L, C, true>(fin, a, xp)
+                             : ghost_mass<L, C, false>(fin, a, xp);
         if (lane == 0)
           ratio_s[p] = top ? (a.tab->Wt + M) / a.tab->Dt : (a.tab->Wb + M) / a.tab->Db;
       }
