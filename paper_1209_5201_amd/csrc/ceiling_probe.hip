@@ -4,7 +4,8 @@
 // memory-side cache kept from the launch before:
 //  - pull_only<L, T>: the update's access pattern with no collision
 //    arithmetic.  Planes of nx*ny elements of T (8, 4 or 2 bytes, the
-//    population formats), one node per lane, blocks of 256 lanes along a
+//    population formats) with the update's plane stride (the node count
+//    rounded up to 64, plus 128), one node per lane, blocks of 256 lanes along a
 //    row, the same XCD-aware block order, each velocity pulled from
 //    (x - e_x, y - e_y) with x periodic, nontemporal stores; over the rows
 //    whose sources all lie inside the grid (N <= y < ny - N).
@@ -104,7 +105,7 @@ template <class L, class T>
 int measure(int nx, int ny, int reps, double* pull_us, double* copy_us, double* pull_bytes,
             double* copy_bytes) {
   if (nx < kBlock || nx % kBlock != 0 || ny <= 2 * L::N || reps < 1) return -1;
-  const size_t plane = size_t(nx) * size_t(ny);
+  const size_t plane = (size_t(nx) * size_t(ny) + 63) / 64 * 64 + 128;
   const size_t elems = size_t(L::Q) * plane;
   if (plane > 0xffffffffull / 2 || (elems * sizeof(T)) % sizeof(f4) != 0) return -1;
   T* buf[2] = {nullptr, nullptr};

@@ -10,8 +10,8 @@
 // Per step, two launches:
 //  1. wall_kernel: one wavefront per (wall, ghost column) gathers the mass
 //     that the post-collision populations send into the N ghost layers of
-//     that column (the numerator of Eq. (eq:dkboundary)), reduces it in FP64
-//     with a butterfly of lane shuffles, and stores ratio = M / D.
+//     that column (the numerator of Eq. (eq:dkboundary)), summing the terms
+//     in FP64 in a fixed order, and stores ratio = M / D.
 //  2. step_kernel: one thread per node pulls f~_q(x, y) = f*_q(x - e_x,
 //     y - e_y); when the source lies in a ghost layer the value is the
 //     re-emitted g^eq_q(u_w, T_w) * ratio of that ghost column (same-step
@@ -1102,8 +1102,8 @@ __device__ __forceinline__ void residual_terms(const double* mom, double* snap, 
 // ---------------------------------------------------------- batched cases --
 // Persistent update of many small channels: workgroup b owns case b and runs
 // its steps itself, so a step costs two workgroup barriers instead of two
-// kernel launches.  Per step: each wavefront reduces the pooled mass of
-// (wall, ghost column) pairs with a lane-shuffle butterfly into LDS,
+// kernel launches.  Per step: each wavefront sums the pooled mass of
+// (wall, ghost column) pairs in FP64 into LDS,
 // barrier, the threads update the case's nodes (pulls from the ping-pong
 // buffers, which stay in cache), barrier.  Steps run in residual windows;
 // after each window the case's fields, mass and residual are formed in the
