@@ -510,15 +510,17 @@ __device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
 // F = a . d f^eq / du; the trapezoidal change of variable of Sec. II applied
 // to collision + force gives g* = g + omega (f^eq - w - g) + tau/(tau+1/2) F
 // with f^eq and F at the moments of f: u = u[f~] + a/2, T = T[f~] + a^2/(4D).
+// relax() = macro() + relax_part() over the whole set + write_fields(); the
+// batched kernel's split nodes call the parts itself (case_nodes_part).
 template <class R>
 struct NeqSums {
   R sxy, qx, qy, qz;  // non-equilibrium sums of the stress and heat flux
 };
 
 // The collision of velocity subset PART (of P; all for PART = -1) given the
-// node's moments m of f~ (turned into those of f under a force).  With MOM,
-// also accumulates the subset's stress and heat-flux sums into ns.  Returns
-// tau/(tau+1/2) of the node.
+// node's moments m of f~ (turned into those of f under a force, in place).
+// With MOM, also returns the subset's stress and heat-flux sums in ns.
+// Returns tau/(tau+1/2) of the node.
 template <class L, class R, bool MOM, bool FORCE, int PART = -1, int P = 1>
 __device__ __forceinline__ R relax_part(R (&g)[L::Q], const StepArgs& a, Macro<R>& m,
                                         NeqSums<R>& ns) {

@@ -60,7 +60,7 @@ struct ReduceArgs {
 // One channel of a batched launch (lbm_batch_step): the step arguments of a
 // context plus its buffers.  Built on the host, copied to the device.
 constexpr int kBatchMaxNx = 64;    // ghost-column ratios of a case live in LDS
-constexpr int kBatchBlock = 256;   // threads per case of the batched kernel
+constexpr int kBatchBlock = 256;   // threads per case of the batched kernel (FP32: 1024)
 struct CaseDesc {
   StepArgs a;           // fin/fout/step are set per step from f, cur, steps
   void* f[2];

@@ -57,9 +57,8 @@ def percentile(vals, p):
 
 
 class Server:
-    # cost of one step of the most expensive case (121 velocities, two
-    # passes of 256 threads over 512 nodes) and launch length in its windows
-    REF_COST = 121 * 2
+    # launch length: REF_WINDOWS windows of the most expensive case (D3Q121,
+    # 512 nodes; see _step_cost)
     REF_WINDOWS = 4
 
     def __init__(self, prec: str = "fp32", window: int = 100, tol: float = 1e-8,
@@ -81,12 +80,33 @@ class Server:
     def _footprint(self, req) -> int:
         return _l.lbm_required_bytes(req["lattice"], req.get("nx", 1), req["ny"], self.prec)
 
+    def _step_cost(self, lattice: str, nodes: int, force: bool) -> float:
+        """Time of one step of a case in the batched kernel, in microseconds
+        (measured on MI355X; only the per-launch budgets use it, and they do
+        not change results).  The FP32 instance without a force gives a
+        case 1024 threads and splits D3Q121 nodes over four groups (256
+        nodes per pass; 2-D sets 1024 per pass): about 16 us plus 7 us per
+        further pass for D3Q121, 3.6 us plus 1.5 us per pass for the 2-D
+        sets.  The other instances run 256 threads and whole nodes."""
+        big = lattice == "D3Q121"
+        if self.prec == "fp32" and not force:
+            per_pass = 256 if big else 1024
+        else:
+            per_pass = 256
+        passes = -(-nodes // per_pass)
+        base, extra = (16.0, 7.0) if big else (3.6, 1.5)
+        if not (self.prec == "fp32" and not force):
+            base, extra = (2.0 * base, 2.0 * extra) if big else (base, 2.0 * extra)
+        return base + extra * (passes - 1)
+
     def _budget(self, req) -> int:
         """Steps per launch for a case: REF_WINDOWS windows for the most
-        expensive case, proportionally more for cheaper ones."""
-        Q = {"D2Q16": 16, "D2Q17": 17, "D3Q121": 121}[req["lattice"]]
-        passes = -(-req.get("nx", 1) * req["ny"] // 256)
-        windows = self.ref_windows * max(1, self.REF_COST // (Q * passes))
+        expensive case, proportionally more for cheaper ones, so that the
+        cases of a launch take about the same time."""
+        force = bool(req.get("force") or req.get("umax"))
+        ref = self._step_cost("D3Q121", 512, force)
+        cost = self._step_cost(req["lattice"], req.get("nx", 1) * req["ny"], force)
+        windows = max(1, int(round(self.ref_windows * ref / cost)))
         return self.window * windows
 
     def _open(self, req):
