@@ -108,3 +108,25 @@ def test_law_is_refused_where_it_does_not_apply():
     with pytest.raises(lbm.LbmError):
         free.set_viscosity_law(0.5)
     free.close()
+
+
+def test_fp32_split_node_batched_with_law_and_accommodation():
+    """The FP32 batched kernel splits each D3Q121 node over four groups of
+    waves (velocity subsets with partial moment sums combined in LDS); 300
+    rows take two passes of 256 nodes.  With the viscosity law and partial
+    accommodation on both walls: against the FP64 oracle at the FP32 bar,
+    and against the same case on the per-node kernel, which sums each node's
+    moments in one lane (the two differ only in rounding order)."""
+    say("case split node batched fp32 D3Q121 ny 300 law + accommodation")
+    g, o = pair(1, 300, 0.7, 0.5, prec="fp32", seed=31)
+    h, _ = pair(1, 300, 0.7, 0.5, prec="fp32", seed=31)
+    for c in (g, h):
+        c.set_accommodation(0.6, 0.85)
+    o.alpha = (0.6, 0.85)
+    lbm.lbm_batch_step([g.ctx], 40)
+    h.step(40)
+    o.run(40)
+    assert max_err(g.moments(), o.moments(), 1e-9) <= 1e-5
+    assert max_err(g.moments(), h.moments(), 1e-9) <= 1e-5
+    g.close()
+    h.close()
