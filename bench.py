@@ -275,7 +275,7 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU only: the single-GPU share is the "
               "workload (a multi-GPU run would split x into slabs with a "
-              "3-column halo exchange, which this build does not implement)",
+              "3-column halo exchange, which this library does not implement)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -81,7 +81,7 @@ typedef enum {
     LBM_EDEVICE = -3,       /* HIP runtime error */
     LBM_ENONFINITE = -4,    /* a NaN/Inf appeared in the moments */
     LBM_ENEGATIVE = -5,     /* negative wall Maxwellian (positivity lost) */
-    LBM_EUNSUPPORTED = -6   /* valid request this build does not provide */
+    LBM_EUNSUPPORTED = -6   /* valid request this library does not provide */
 } lbm_status;
 
 /* Output fields of lbm_field (Eq. (eq:summac)): density, velocity,
