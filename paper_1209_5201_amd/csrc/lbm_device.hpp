@@ -422,6 +422,47 @@ struct EqCoef {
 
   // poly at the rest velocity (c = 0, x = 0)
   __host__ __device__ R poly0() const { return k0a; }
+
+  // force<EE> for the pair c, -c: x and a.c change sign together, so with
+  // dP/dx = Pe + Po and dP/d(u.u) = Ue + Uo split into parts even and odd
+  // in x, F(c) / w = Se + So and F(-c) / w = Se - So, where
+  // Se = (a.c) Po + 2 (a.u) Ue and So = (a.c) Pe + 2 (a.u) Uo.
+  template <int EE>
+  __host__ __device__ void force_pair(R x, R ac, R au, R& plus, R& minus) const {
+    constexpr R cc = R(L::R * L::R * EE);
+    R K1, K2;
+    if constexpr (L::THERMAL) {
+      K1 = k1a + cc * k1b;
+      K2 = k2a + cc * k2b;
+    } else {
+      K1 = k1a;
+      K2 = k2a;
+    }
+    const R x2 = x * x;
+    R pe, po, ue, uo;
+    if constexpr (L::EQ >= 4) {
+      pe = K1 + R(3) * k3 * x2;
+      po = x * (R(2) * K2 + R(4) * k4 * x2);
+      ue = d0a + cc * d0b + d2 * x2;
+      uo = d1 * x;
+    } else if constexpr (L::EQ == 3) {
+      pe = K1 + R(3) * k3 * x2;
+      po = R(2) * K2 * x;
+      ue = d0a;
+      uo = d1 * x;
+    } else {
+      pe = K1;
+      po = R(2) * K2 * x;
+      ue = d0a;
+      uo = R(0);
+    }
+    const R se = ac * po + R(2) * au * ue, so = ac * pe + R(2) * au * uo;
+    plus = se + so;
+    minus = se - so;
+  }
+
+  // force at the rest velocity (c = 0): 2 (a.u) dP/d(u.u) at x = 0
+  __host__ __device__ R force0(R au) const { return R(2) * au * d0a; }
 };
 
 template <class R>
@@ -551,18 +592,10 @@ __device__ __forceinline__ R relax_part(R (&g)[L::Q], const StepArgs& a, Macro<R
   const R au = fax * m.ux + fay * m.uy + faz * m.uz;
   R sxy = 0, qx = 0, qy = 0, qz = 0;
   // velocity q at x = c_q.u, with geq = f^eq_q - w_q
-  auto finish = [&](auto qc, R x, R geq) {
+  // F: the force term of velocity q (zero without a force)
+  auto finish = [&](auto qc, R geq, R F) {
     constexpr int q = decltype(qc)::value;
     constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
-    constexpr int EE = ex * ex + ey * ey + ez * ez;
-    R F = R(0);
-    if constexpr (FORCE) {
-      R ac = R(0);
-      ac = add_scaled<ex>(ac, fax);
-      ac = add_scaled<ey>(ac, fay);
-      ac = add_scaled<ez>(ac, faz);
-      F = R(L::W[q]) * k.template force<EE>(x, r * ac, au);
-    }
     if constexpr (MOM) {
       // f~ - f^eq (+ F/2 under a force: f - f^eq = tau/(tau+1/2) (f~ + F/2 - f^eq))
       const R neq = FORCE ? g[q] - geq + R(0.5) * F : g[q] - geq;
@@ -586,16 +619,19 @@ __device__ __forceinline__ R relax_part(R (&g)[L::Q], const StepArgs& a, Macro<R
     constexpr int o = opposite<L>(q);
     static_assert(o >= 0, "velocity set not closed under c -> -c");
     constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
+    constexpr int EE = ex * ex + ey * ey + ez * ez;
     if constexpr (!in_part<L, PART, P>(q)) {
       // another part's velocity
     } else if constexpr (o == q) {
-      finish(qc, R(0), R(L::W[q]) * k.poly0());
+      finish(qc, R(L::W[q]) * k.poly0(), FORCE ? R(L::W[q]) * k.force0(au) : R(0));
     } else if constexpr (q < o) {
       const R x = dot_e<ex, ey, ez>(sx, sy, sz);
-      R plus, minus;
-      k.template poly_pair<ex * ex + ey * ey + ez * ez>(x, plus, minus);
-      finish(qc, x, R(L::W[q]) * plus);
-      finish(std::integral_constant<int, o>{}, -x, R(L::W[o]) * minus);
+      R plus, minus, fplus = R(0), fminus = R(0);
+      k.template poly_pair<EE>(x, plus, minus);
+      if constexpr (FORCE)
+        k.template force_pair<EE>(x, r * dot_e<ex, ey, ez>(fax, fay, faz), au, fplus, fminus);
+      finish(qc, R(L::W[q]) * plus, R(L::W[q]) * fplus);
+      finish(std::integral_constant<int, o>{}, R(L::W[o]) * minus, R(L::W[o]) * fminus);
     }
   };
   static_for<0, L::Q>(body);
