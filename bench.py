@@ -172,8 +172,8 @@ def serving(n_requests: int, rate: float, baseline_cases: int):
 
 def precision_table(torch, steps_2d: int = 200, steps_3d: int = 60):
     """MLUPS and algorithmic HBM rate of the fused update per velocity set and
-    storage format: the bulk D2Q17 2048^2 case and the D3Q121 1024^2 case
-    (walls -0.1 / +0.1, Kn 0.05).  Wall clock over back-to-back steps (one
+    storage format: the bulk 2048^2 case on D2Q16 and D2Q17, and the D3Q121
+    1024^2 case (walls -0.1 / +0.1, Kn 0.05).  Wall clock over back-to-back steps (one
     launch per step); fields refreshed once at the end.  Each row also gives
     the same-run pull ceiling for its element size and the fraction of it the
     update reaches."""
@@ -181,6 +181,7 @@ def precision_table(torch, steps_2d: int = 200, steps_3d: int = 60):
     from paper_1209_5201_amd import workloads as W
     rows = []
     for lat, nx, ny, steps, walls in (
+            ("D2Q16", 2048, 2048, steps_2d, (W.C3["bottom"], W.C3["top"])),
             ("D2Q17", 2048, 2048, steps_2d, (W.C3["bottom"], W.C3["top"])),
             ("D3Q121", W.C5["nx"], W.C5["ny"], steps_3d, (W.C5["bottom"], W.C5["top"]))):
         Q = lbm.lbm_lattice_info(lat)["Q"]
