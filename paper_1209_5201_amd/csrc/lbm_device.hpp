@@ -346,30 +346,6 @@ struct EqCoef {
     return c;
   }
 
-  // Body-force term (f^eq's directional derivative in u at fixed rho, T)
-  // over w_q: F_q / w_q = (a.c) dP/dx + 2 (a.u) dP/d(u.u), P = f^eq_q / w_q.
-  template <int EE>
-  __host__ __device__ R force(R x, R ac, R au) const {
-    constexpr R cc = R(L::R * L::R * EE);
-    R K1, K2;
-    if constexpr (L::THERMAL) {
-      K1 = k1a + cc * k1b;
-      K2 = k2a + cc * k2b;
-    } else {
-      K1 = k1a;
-      K2 = k2a;
-    }
-    R px;
-    if constexpr (L::EQ >= 4) px = K1 + x * (R(2) * K2 + x * (R(3) * k3 + x * (R(4) * k4)));
-    else if constexpr (L::EQ == 3) px = K1 + x * (R(2) * K2 + x * (R(3) * k3));
-    else px = K1 + x * (R(2) * K2);
-    R puu;
-    if constexpr (L::EQ >= 4) puu = d0a + cc * d0b + x * (d1 + x * d2);
-    else if constexpr (L::EQ == 3) puu = d0a + x * d1;
-    else puu = d0a;
-    return ac * px + R(2) * au * puu;
-  }
-
   // (f^eq_q - w_q) / w_q at x = c_q.u, for |e_q|^2 = EE.
   template <int EE>
   __host__ __device__ R poly(R x) const {
@@ -423,7 +399,9 @@ struct EqCoef {
   // poly at the rest velocity (c = 0, x = 0)
   __host__ __device__ R poly0() const { return k0a; }
 
-  // force<EE> for the pair c, -c: x and a.c change sign together, so with
+  // Body-force term (f^eq's directional derivative in u at fixed rho, T)
+  // over w_q: F_q / w_q = (a.c) dP/dx + 2 (a.u) dP/d(u.u), P = f^eq_q / w_q,
+  // for the pair c, -c at once: x and a.c change sign together, so with
   // dP/dx = Pe + Po and dP/d(u.u) = Ue + Uo split into parts even and odd
   // in x, F(c) / w = Se + So and F(-c) / w = Se - So, where
   // Se = (a.c) Po + 2 (a.u) Ue and So = (a.c) Pe + 2 (a.u) Uo.
