@@ -170,6 +170,7 @@ struct CF64 {
   static constexpr bool kRandom = false;
   static constexpr int kRandBits = 0;
   static constexpr bool kWallRowsFirst = false;  // row order of the row-tiled update
+  static constexpr int kScale = 1;  // registers hold (f - w) * kScale
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
   }
@@ -187,6 +188,7 @@ struct CF32 {
   static constexpr bool kRandom = false;
   static constexpr int kRandBits = 0;
   static constexpr bool kWallRowsFirst = false;  // row order of the row-tiled update
+  static constexpr int kScale = 1;  // registers hold (f - w) * kScale
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
   }
@@ -209,6 +211,7 @@ struct CF32S {
   static constexpr bool kRandom = true;
   static constexpr int kRandBits = 29;
   static constexpr bool kWallRowsFirst = true;  // row order of the row-tiled update
+  static constexpr int kScale = 1;  // registers hold (f - w) * kScale
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     return double(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0)));
   }
@@ -237,6 +240,7 @@ struct CBF16 {
   static constexpr bool kRandom = true;
   static constexpr int kRandBits = 16;
   static constexpr bool kWallRowsFirst = true;  // row order of the row-tiled update
+  static constexpr int kScale = 1;  // registers hold (f - w) * kScale
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
     return __uint_as_float(h << 16);
@@ -255,10 +259,13 @@ struct CBF16 {
 };
 
 // FP16 keeps (f - w) * 2^12: deviations |f - w| < 1 fit its range (65504)
-// and small ones stay above its normal limit 2^-14.  The scale is a
-// compile-time constant: a scale read from memory would have to be re-read
-// after every population store (the stores may alias it), each re-read
-// waiting for all stores in flight.
+// and small ones stay above its normal limit 2^-14.  The update works on the
+// scaled values themselves (kScale: every step is linear in the deviations
+// and a power-of-two scale commutes with rounding, so the results match
+// unscaled arithmetic to rounding), and loads and stores carry no multiply.  The
+// scale is a compile-time constant: one read from memory would have to be
+// re-read after every population store (the stores may alias it), each
+// re-read waiting for all stores in flight.
 struct CFP16 {
   using S = _Float16;
   using R = float;
@@ -266,13 +273,13 @@ struct CFP16 {
   static constexpr bool kRandom = true;
   static constexpr int kRandBits = 13;
   static constexpr bool kWallRowsFirst = true;  // row order of the row-tiled update
-  static constexpr float kScale = 4096.0f;
+  static constexpr int kScale = 4096;  // registers hold (f - w) * kScale
   __device__ static R ld(Rsrc r, uint32_t vo, uint32_t so, const Tables*) {
     const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
-    return float(__builtin_bit_cast(_Float16, h)) * (1.0f / kScale);
+    return float(__builtin_bit_cast(_Float16, h));
   }
   // Stochastic rounding to FP16's 10-bit significand: add 13 random bits
-  // below the kept ones to the scaled float's sign-magnitude word (a carry
+  // below the kept ones to the (scaled) float's sign-magnitude word (a carry
   // rounds the magnitude up, for either sign) and clear them.  In FP16's
   // normal range [2^-14, 65504] the result is an FP16 value and the
   // conversion exact; below it (deviations under 2^-26 with the scale) the
@@ -282,7 +289,7 @@ struct CFP16 {
   template <int POL>
   __device__ static void st(Rsrc r, uint32_t vo, uint32_t so, R g, const Tables*,
                             uint32_t rnd) {
-    const uint32_t u = (__float_as_uint(g * kScale) + (rnd & 0x1fffu)) & 0xffffe000u;
+    const uint32_t u = (__float_as_uint(g) + (rnd & 0x1fffu)) & 0xffffe000u;
     const _Float16 h = _Float16(__uint_as_float(u));
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, h), r, vo, so, POL);
   }
@@ -507,10 +514,6 @@ __device__ __forceinline__ Macro<R> macro_from(const Sums<R>& t) {
   return m;
 }
 
-template <class L, class R, class G = R>
-__device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
-  return macro_from<L, R>(sums<L, R, G>(g));
-}
 
 // g* = g - omega (g - (f^eq - w)), in place.  With MOM, also writes the
 // output fields of the pre-collision state f~ at node n (Eq. (eq:summac)):
@@ -529,8 +532,9 @@ __device__ __forceinline__ Macro<R> macro(const G (&g)[L::Q]) {
 // F = a . d f^eq / du; the trapezoidal change of variable of Sec. II applied
 // to collision + force gives g* = g + omega (f^eq - w - g) + tau/(tau+1/2) F
 // with f^eq and F at the moments of f: u = u[f~] + a/2, T = T[f~] + a^2/(4D).
-// relax() = macro() + relax_part() over the whole set + write_fields(); the
-// batched kernel's split nodes call the parts itself (case_nodes_part).
+// relax() = sums() + macro_from() + relax_part() over the whole set +
+// write_fields(); the batched kernel's split nodes call the parts itself
+// (case_nodes_part).
 template <class R>
 struct NeqSums {
   R sxy, qx, qy, qz;  // non-equilibrium sums of the stress and heat flux
@@ -540,7 +544,7 @@ struct NeqSums {
 // node's moments m of f~ (turned into those of f under a force, in place).
 // With MOM, also returns the subset's stress and heat-flux sums in ns.
 // Returns tau/(tau+1/2) of the node.
-template <class L, class R, bool MOM, bool FORCE, int PART = -1, int P = 1>
+template <class L, class R, bool MOM, bool FORCE, int PART = -1, int P = 1, int SC = 1>
 __device__ __forceinline__ R relax_part(R (&g)[L::Q], const StepArgs& a, Macro<R>& m,
                                         NeqSums<R>& ns) {
   R fax = 0, fay = 0, faz = 0;
@@ -601,19 +605,20 @@ __device__ __forceinline__ R relax_part(R (&g)[L::Q], const StepArgs& a, Macro<R
     if constexpr (!in_part<L, PART, P>(q)) {
       // another part's velocity
     } else if constexpr (o == q) {
-      finish(qc, R(L::W[q]) * k.poly0(), FORCE ? R(L::W[q]) * k.force0(au) : R(0));
+      finish(qc, R(L::W[q] * SC) * k.poly0(), FORCE ? R(L::W[q] * SC) * k.force0(au) : R(0));
     } else if constexpr (q < o) {
       const R x = dot_e<ex, ey, ez>(sx, sy, sz);
       R plus, minus, fplus = R(0), fminus = R(0);
       k.template poly_pair<EE>(x, plus, minus);
       if constexpr (FORCE)
         k.template force_pair<EE>(x, r * dot_e<ex, ey, ez>(fax, fay, faz), au, fplus, fminus);
-      finish(qc, R(L::W[q]) * plus, R(L::W[q]) * fplus);
-      finish(std::integral_constant<int, o>{}, R(L::W[o]) * minus, R(L::W[o]) * fminus);
+      finish(qc, R(L::W[q] * SC) * plus, R(L::W[q] * SC) * fplus);
+      finish(std::integral_constant<int, o>{}, R(L::W[o] * SC) * minus, R(L::W[o] * SC) * fminus);
     }
   };
   static_for<0, L::Q>(body);
-  ns = NeqSums<R>{sxy, qx, qy, qz};
+  constexpr R inv = R(1.0 / SC);
+  ns = NeqSums<R>{sxy * inv, qx * inv, qy * inv, qz * inv};
   return kf;
 }
 
@@ -645,12 +650,19 @@ __device__ __forceinline__ void write_fields(double* mom, long long nodes, long 
   }
 }
 
-template <class L, class R, bool MOM = false, bool FORCE = false>
+// SC: the deviations in g are scaled by SC (a power of two; the codec's
+// kScale); the moments, fields and f^eq are those of the unscaled values.
+template <class L, class R, bool MOM = false, bool FORCE = false, int SC = 1>
 __device__ __forceinline__ void relax(R (&g)[L::Q], const StepArgs& a, double* mom = nullptr,
                                       long long nodes = 0, long long n = 0) {
-  Macro<R> m = macro<L, R>(g);
+  Sums<R> t = sums<L, R>(g);
+  if constexpr (SC != 1) {
+    constexpr R inv = R(1.0 / SC);
+    t = Sums<R>{t.drho * inv, t.mx * inv, t.my * inv, t.mz * inv, t.e2 * inv};
+  }
+  Macro<R> m = macro_from<L, R>(t);
   NeqSums<R> ns;
-  const R kf = relax_part<L, R, MOM, FORCE>(g, a, m, ns);
+  const R kf = relax_part<L, R, MOM, FORCE, -1, 1, SC>(g, a, m, ns);
   if constexpr (MOM) write_fields<L, R>(mom, nodes, n, m, kf, ns);
 }
 
@@ -756,7 +768,7 @@ __device__ __forceinline__ double ghost_mass(Rsrc fin, const StepArgs& a, int xp
                         uint32_t(T.q) * uint32_t(a.plane) * C::B, a.tab));
   };
   static_for<0, W::NT>(body);
-  return acc;
+  return acc * (1.0 / C::kScale);
 }
 
 template <class L, class C>
@@ -833,9 +845,9 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
       if constexpr (!in_part<L, PART, P>(q)) return;
       const int ys = y - ey;
       if (ey > 0 && ys < 0)
-        f[q] = R(wtab[q] * ratio(0, ex) - L::W[q]);
+        f[q] = R((wtab[q] * ratio(0, ex) - L::W[q]) * C::kScale);
       else if (ey < 0 && ys >= a.ny)
-        f[q] = R(wtab[L::Q + q] * ratio(1, ex) - L::W[q]);
+        f[q] = R((wtab[L::Q + q] * ratio(1, ex) - L::W[q]) * C::kScale);
       else
         f[q] = C::ld(fin, (uint32_t(ys) * nx + uint32_t(xw[ex + NS])) * C::B, uint32_t(q) * pb,
                      a.tab);
@@ -862,10 +874,10 @@ __device__ __forceinline__ void pull(typename C::R (&f)[L::Q], const StepArgs& a
       if constexpr (!in_part<L, PART, P>(q)) {
         // another part's velocity
       } else if constexpr (ey > 0) {  // bottom wall (y - e_y < 0)
-        const R v = R(wtab[q] * ratio(0, ex) - L::W[q]);
+        const R v = R((wtab[q] * ratio(0, ex) - L::W[q]) * C::kScale);
         f[q] = y - ey < 0 ? v : f[q];
       } else if constexpr (ey < 0) {  // top wall (y - e_y >= ny)
-        const R v = R(wtab[L::Q + q] * ratio(1, ex) - L::W[q]);
+        const R v = R((wtab[L::Q + q] * ratio(1, ex) - L::W[q]) * C::kScale);
         f[q] = y - ey >= a.ny ? v : f[q];
       }
     };
@@ -964,7 +976,7 @@ __device__ __forceinline__ double ghost_column_deviation(const StepArgs& a, int 
                         uint32_t(T.q) * uint32_t(a.plane) * C::B, a.tab));
   };
   static_for<0, W::NT>(body);
-  return acc;
+  return acc * (1.0 / C::kScale);
 }
 
 // Any grid shape: one thread per node on a linear node index; the ghost
@@ -991,7 +1003,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
   pull<L, C>(f, a, y, xw, wtab_s,
              [&](int wall, int ex) { return a.ratio[wall * a.nx + xw[ex + NS]]; });
   wall_specular<L, C>(f, a, y, xw);
-  relax<L, R, MOM, FORCE>(f, a, a.mom, nodes, n);
+  relax<L, R, MOM, FORCE, C::kScale>(f, a, a.mom, nodes, n);
   store<L, C>(f, a, uint32_t(n));
 }
 
@@ -1046,7 +1058,7 @@ __global__ __launch_bounds__(kBlock) void step_rows_kernel(StepArgs a) {
   if (bottom || top) wall_specular<L, C>(f, a, y, xw);
   const long long nodes = (long long)a.nx * a.ny;
   const uint32_t n = uint32_t(y) * uint32_t(a.nx) + uint32_t(x);
-  relax<L, R, MOM, FORCE>(f, a, a.mom, nodes, n);
+  relax<L, R, MOM, FORCE, C::kScale>(f, a, a.mom, nodes, n);
   store<L, C>(f, a, n);
 }
 
@@ -1074,10 +1086,10 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double* 
     constexpr int q = decltype(qc)::value;
     constexpr int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
     const double x = r * (ex * ux + ey * uy + ez * uz);
-    f[q] = R(L::W[q] * k.template poly<ex * ex + ey * ey + ez * ez>(x));  // f^eq - w
+    f[q] = R(L::W[q] * k.template poly<ex * ex + ey * ey + ez * ez>(x) * C::kScale);  // f^eq - w
   };
   static_for<0, L::Q>(body);
-  relax<L, R, true, FORCE>(f, a, a.mom, nodes, n);
+  relax<L, R, true, FORCE, C::kScale>(f, a, a.mom, nodes, n);
   store<L, C>(f, a, uint32_t(n));
 }
 
@@ -1144,7 +1156,7 @@ __device__ __forceinline__ void case_nodes(const StepArgs& a, int nodes, const d
     pull<L, C>(f, a, y, xw, wtab_s,
                [&](int wall, int ex) { return ratio_s[wall * a.nx + xw[ex + NS]]; });
     wall_specular<L, C>(f, a, y, xw);
-    relax<L, R, MOM, FORCE>(f, a, a.mom, nodes, n);
+    relax<L, R, MOM, FORCE, C::kScale>(f, a, a.mom, nodes, n);
     store<L, C, kStoreCached>(f, a, uint32_t(n));
   }
 }
@@ -1213,9 +1225,10 @@ __device__ __forceinline__ void case_nodes_part(const StepArgs& a, int nodes,
         v[k] = psum[k * kSlots + slot];
         for (int p = 1; p < P; ++p) v[k] += psum[(p * 5 + k) * kSlots + slot];
       }
-      m = macro_from<L, R>(Sums<R>{v[0], v[1], v[2], v[3], v[4]});
+      constexpr R inv = R(1.0 / C::kScale);
+      m = macro_from<L, R>(Sums<R>{v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv, v[4] * inv});
       NeqSums<R> ns;
-      kf = relax_part<L, R, MOM, FORCE, PART, P>(f, a, m, ns);
+      kf = relax_part<L, R, MOM, FORCE, PART, P, C::kScale>(f, a, m, ns);
       store<L, C, kStoreCached, PART, P>(f, a, uint32_t(n));
       if constexpr (MOM) {
         pneq[(PART * 4 + 0) * kSlots + slot] = ns.sxy;
